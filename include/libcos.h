@@ -1,0 +1,153 @@
+/*
+ * libcos.h -- connected-diagram sums of the SU(N) Hubbard model (CoS / SB-CoS,
+ * arXiv 2507.12349) on AMD Instinct MI355X (gfx950), FP64 throughout.
+ *
+ * What is computed (Results, "Theoretical Constructions"; Methods, Alg. 2/3).
+ * A configuration has n interaction vertices, 1 <= n <= COS_NMAX.  Vertex k
+ * carries two points, k and k+n, joined by the interaction line (the pairs
+ * I = {(i, i+n)} of Alg. 1-3).  Propagator matrices are indexed by vertex:
+ * G_l[k][j] is the propagator from vertex k to vertex j for flavour l, with an
+ * equal-time pair read as tau = 0^- (Methods, equal-time propagators).  For
+ * every permutation pi of the points (minus the shift points, below) and every
+ * assignment of one flavour per cycle, the term is
+ *     prod_cycles ( w * prod_{p in cycle} G_l[vertex(p)][vertex(pi(p))] )
+ *   * prod_shift_points ( -sigma_{l(partner)} )
+ * and the library returns the sum of the terms whose diagram is connected
+ * (the graph on vertices that joins the vertices of each cycle is
+ * connected).  The shift points implement the SB-CoS "shift heads": a point
+ * that is not on a propagator cycle, carries the weight -sigma of the flavour
+ * of the cycle through its partner, at most one per vertex (Results, SB-CoS;
+ * Alg. 3).  No prefactor ((-U)^n/n!, integrals) is included.
+ *
+ * Variants
+ *   COS_UNIFORM : one matrix G (uniform SU(N)); every closed cycle carries the
+ *                 factor w * nflav (Alg. 2 closes with -N_f for w = -1).  With
+ *                 COS_F_STUBS every shift point carries -sigma[0].
+ *   COS_FLAVOUR : nflav matrices G_l (flavour-dependent chemical potentials or
+ *                 shifts, Alg. 3); every cycle carries w; with COS_F_STUBS a
+ *                 shift point carries -sigma[l].
+ * The physical loop weight is w = -1.
+ *
+ * Memory and ownership.  The caller owns every buffer; the library keeps no
+ * caller pointer beyond a call (for the asynchronous calls: beyond the
+ * completion of the work queued on the stream).  "d_" arguments are device
+ * pointers on the current HIP device, others are host pointers.  Matrices are
+ * FP64, row-major: config c, matrix g (0 for COS_UNIFORM, the flavour
+ * otherwise), entry [k][j] is at d_G[d_Goff[c] + (g*n_c + k)*n_c + j].
+ * Shift weights: d_stub[c*nstub + g], nstub = 1 (COS_UNIFORM) or nflav.
+ *
+ * Errors.  Every function returns cos_status.  Arguments are validated before
+ * any device work (COS_EINVAL / COS_ERANGE); a failing HIP call returns
+ * COS_EDEVICE; detail text for the calling thread is in cos_last_error().
+ * No exception crosses the ABI.  Calls on different streams may overlap; a
+ * batch handle must not be used by two streams at once (it owns the
+ * workspace its kernels write).
+ */
+#ifndef LIBCOS_H
+#define LIBCOS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    COS_OK = 0,
+    COS_EINVAL = -1,        /* null pointer, bad variant / flags / sizes */
+    COS_ERANGE = -2,        /* n outside [1, COS_NMAX], nflav outside [1, COS_FMAX] */
+    COS_ENOMEM = -3,        /* device or host allocation failed */
+    COS_EDEVICE = -4,       /* a HIP call failed */
+    COS_EUNSUPPORTED = -5   /* no usable gfx950 device */
+} cos_status;
+
+#define COS_NMAX 12
+#define COS_FMAX 16
+
+enum { COS_UNIFORM = 0, COS_FLAVOUR = 1 };
+enum { COS_F_STUBS = 1 };
+
+typedef struct cos_batch_s *cos_batch_t;
+
+/* Plan a batch of nconf configurations with orders n[c] (host array, read
+ * during the call only).  Builds (or reuses) the per-order state tables,
+ * uploads the schedule (configurations ordered by decreasing work) and
+ * allocates the workspace on the current device.  The handle can then be
+ * used for any number of asynchronous calls, including under stream capture.
+ * Returns COS_ERANGE for an order outside [1, COS_NMAX], COS_EINVAL for
+ * nconf < 1 or a bad variant / flag. */
+cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
+                            int32_t variant, int32_t flags, cos_batch_t *out);
+cos_status cos_batch_destroy(cos_batch_t b);
+
+/* Forward sum for every configuration of the batch, asynchronous on `stream`
+ * (a hipStream_t, NULL = default stream).  One persistent launch per distinct
+ * order in the batch (one launch when all orders are equal), largest order
+ * first; each workgroup takes configurations from a work queue until none is
+ * left.  No host synchronisation, no allocation: capturable in a graph.
+ * d_Goff may be NULL when the configurations are stored back to back.
+ * d_stub is required iff the batch was planned with COS_F_STUBS.
+ * Writes d_out[c] = S_c. */
+cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
+                                     const double *d_stub, double cycle_weight, double *d_out,
+                                     void *stream);
+
+/* Reverse mode: given d_out_bar[c] = dL/dS_c, writes d_G_bar (layout of d_G)
+ * = dL/dG and, with COS_F_STUBS, d_stub_bar (layout of d_stub) = dL/dsigma.
+ * The forward pass is recomputed inside; d_out (optional, may be NULL)
+ * receives S_c.  Asynchronous on `stream`. */
+cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
+                                     const double *d_stub, double cycle_weight,
+                                     const double *d_out_bar, double *d_out, double *d_G_bar,
+                                     double *d_stub_bar, void *stream);
+
+/* One configuration from HOST buffers (G: nmat*n*n, stub: nstub or NULL when
+ * flags lacks COS_F_STUBS); copies to the device, runs the GPU kernel,
+ * synchronises and writes *out.  Convenience for small callers and tests. */
+cos_status cos_connected_sum(int32_t n, int32_t nflav, int32_t variant, int32_t flags,
+                             const double *G, const double *stub, double cycle_weight,
+                             double *out);
+
+/* Free propagator matrices on the device (Methods, square-lattice model):
+ * xi_g(k) = -2 t (cos kx + cos ky) - mu[g] + alpha[g] on k = 2 pi (mx, my)/L,
+ * G(k, tau) = -exp(-xi tau)(1 - nF) for tau > 0 and exp(-xi tau) nF for
+ * tau <= 0 (an equal-time pair is 0^-), G_g[k][j] = L^-2 sum_k
+ * cos(k.(r_k - r_j)) G(k, tau_k - tau_j).  d_dG (may be NULL) receives
+ * dG_g/dxi for a uniform move of xi_g (so d/dmu_g = -d/dxi).
+ * d_sites: int32 [sum n][2] lattice coordinates in [0, L), 1 <= L <= 32; d_tau [sum n];
+ * d_voff[c]: first vertex of config c; mu, alpha: HOST arrays [nmat].
+ * Output layout as d_G above with nmat matrices per configuration. */
+cos_status cos_build_g0(int32_t nconf, const int32_t *d_n, const int64_t *d_voff,
+                        const int32_t *d_sites, const double *d_tau, int32_t L, double t,
+                        double beta, int32_t nmat, const double *mu, const double *alpha,
+                        const int64_t *d_Goff, double *d_G, double *d_dG, void *stream);
+
+/* Chain rule to the chemical potential and the shift (Methods: xi = eps -
+ * mu + alpha, shift weight sigma = alpha / U).  Per configuration c and
+ * matrix g: xb = sum_kj G_bar[g][k][j] * dG[g][k][j];
+ *   d_mu_bar[c*nmat + g]    = -xb
+ *   d_alpha_bar[c*nmat + g] = +xb + stub_bar[c*nstub + g] / U   (stub_bar may be NULL)
+ * For COS_UNIFORM (nmat = 1) the per-flavour shift derivative at equal shifts
+ * is d_alpha_bar / nflav by flavour symmetry. */
+cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat,
+                              const int64_t *d_Goff, const double *d_G_bar, const double *d_dG,
+                              const double *d_stub_bar, int32_t nstub, double U,
+                              double *d_mu_bar, double *d_alpha_bar, void *stream);
+
+/* Plan counts for order n, per flavour (exact integers, host only):
+ * states, extension transitions, closes, shift transitions, masks, rows
+ * (a row = one (mask, head) pair). */
+cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
+                           int64_t *shift_edges, int64_t *masks, int64_t *rows);
+
+/* Diagnostics. */
+const char *cos_status_string(cos_status s);
+const char *cos_last_error(void);
+/* Frees cached state tables of every device.  Outstanding batch handles stay
+ * valid only until destroyed; call after all work has completed. */
+cos_status cos_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIBCOS_H */

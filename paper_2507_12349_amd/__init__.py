@@ -1,0 +1,18 @@
+"""MI355X-native connected-diagram sums of the SU(N) Hubbard model (CoS / SB-CoS,
+arXiv 2507.12349).
+
+The work runs in hand-written HIP kernels for gfx950 behind the C ABI of
+``include/libcos.h`` (``libcos.so``); ``_binding`` is the thin ctypes layer and
+``autograd`` the torch.autograd wrappers.  Names of the binding are loaded on
+first use: touching any of them without the built library raises ImportError
+(there is no CPU fallback).  ``workloads`` (seeded inputs) needs no library.
+"""
+_BINDING = {"Batch", "CosError", "connected_sum_host", "plan_counts", "build_g0", "chain_mu_shift",
+            "UNIFORM", "FLAVOUR", "F_STUBS", "NMAX", "FMAX", "LIB_PATH", "EXPORTED", "lib"}
+
+
+def __getattr__(name):
+    if name in _BINDING:
+        from . import _binding
+        return getattr(_binding, name)
+    raise AttributeError("module %r has no attribute %r" % (__name__, name))

@@ -1,0 +1,166 @@
+"""ctypes binding of libcos.so (argument marshalling only).
+
+Every computation runs in the HIP kernels of ``csrc/``; this module converts
+torch tensors / numpy arrays to pointers and status codes to exceptions.
+Importing it without a built ``libcos.so`` raises ImportError: there is no
+CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcos.so")
+
+UNIFORM, FLAVOUR = 0, 1
+F_STUBS = 1
+NMAX, FMAX = 12, 16
+
+EXPORTED = (
+    "cos_batch_create", "cos_batch_destroy", "cos_connected_sum_batched",
+    "cos_connected_sum_adjoint", "cos_connected_sum", "cos_build_g0", "cos_chain_mu_shift",
+    "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
+)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libcos.so is not built (%s); run __graft_entry__.build() or "
+                          "python paper_2507_12349_amd/csrc/build.py" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, d, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+    P64 = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "cos_batch_create": ([i32, p, i32, i32, i32, ctypes.POINTER(p)], i32),
+        "cos_batch_destroy": ([p], i32),
+        "cos_connected_sum_batched": ([p, p, p, p, d, p, p], i32),
+        "cos_connected_sum_adjoint": ([p, p, p, p, d, p, p, p, p, p], i32),
+        "cos_connected_sum": ([i32, i32, i32, i32, p, p, d, p], i32),
+        "cos_build_g0": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p], i32),
+        "cos_chain_mu_shift": ([i32, p, i32, p, p, p, p, i32, d, p, p, p], i32),
+        "cos_plan_counts": ([i32, P64, P64, P64, P64, P64, P64], i32),
+        "cos_status_string": ([i32], ctypes.c_char_p),
+        "cos_last_error": ([], ctypes.c_char_p),
+        "cos_release": ([], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+lib = _load()
+
+
+class CosError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = "%s: %s (%d): %s" % (where, lib.cos_status_string(status).decode(), status,
+                                   lib.cos_last_error().decode())
+        super().__init__(msg)
+
+
+def _check(status: int, where: str):
+    if status != 0:
+        raise CosError(status, where)
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor / numpy array (None -> NULL)."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError("expected a torch tensor or numpy array, got %r" % type(x))
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def plan_counts(n: int) -> dict:
+    vals = [ctypes.c_int64() for _ in range(6)]
+    _check(lib.cos_plan_counts(int(n), *[ctypes.byref(v) for v in vals]), "cos_plan_counts")
+    return dict(zip(("states", "ext", "closes", "stub_edges", "masks", "rows"), [v.value for v in vals]))
+
+
+def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=None, w: float = -1.0) -> float:
+    """One configuration from host arrays (the GPU kernel does the work)."""
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    n = G.shape[-1]
+    flags = F_STUBS if stub is not None else 0
+    st = None if stub is None else np.ascontiguousarray(stub, dtype=np.float64).reshape(-1)
+    out = ctypes.c_double()
+    _check(lib.cos_connected_sum(n, nflav, variant, flags, _ptr(G), _ptr(st), float(w), ctypes.byref(out)),
+           "cos_connected_sum")
+    return out.value
+
+
+class Batch:
+    """Plan for a batch of configurations with orders ``n`` (host sequence)."""
+
+    def __init__(self, n, nflav: int, variant: int = UNIFORM, stubs: bool = False):
+        n = np.ascontiguousarray(np.asarray(n, dtype=np.int32).reshape(-1))
+        self.n = n
+        self.nconf = int(n.size)
+        self.nflav = int(nflav)
+        self.variant = int(variant)
+        self.stubs = bool(stubs)
+        self.nmat = self.nflav if self.variant == FLAVOUR else 1
+        self.nstub = self.nmat
+        h = ctypes.c_void_p()
+        _check(lib.cos_batch_create(self.nconf, _ptr(n), self.nflav, self.variant,
+                                    F_STUBS if self.stubs else 0, ctypes.byref(h)), "cos_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib.cos_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def goff(self):
+        """Element offsets of each configuration's matrices (back-to-back layout)."""
+        sizes = self.nmat * self.n.astype(np.int64) ** 2
+        off = np.zeros(self.nconf, dtype=np.int64)
+        off[1:] = np.cumsum(sizes[:-1])
+        return off, int(sizes.sum())
+
+    def forward(self, G, Goff, stub, w, out, stream=None):
+        _check(lib.cos_connected_sum_batched(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out),
+                                             _stream(stream)), "cos_connected_sum_batched")
+
+    def adjoint(self, G, Goff, stub, w, out_bar, out, G_bar, stub_bar, stream=None):
+        _check(lib.cos_connected_sum_adjoint(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out_bar),
+                                             _ptr(out), _ptr(G_bar), _ptr(stub_bar), _stream(stream)),
+               "cos_connected_sum_adjoint")
+
+
+def build_g0(nconf, n, voff, sites, tau, L, t, beta, mu, alpha, Goff, G, dG=None, stream=None):
+    """Device propagator builder; n, voff, sites, tau, Goff, G, dG are device tensors,
+    mu and alpha host sequences of length nmat."""
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(-1))
+    _check(lib.cos_build_g0(int(nconf), _ptr(n), _ptr(voff), _ptr(sites), _ptr(tau), int(L), float(t),
+                            float(beta), int(mu.size), _ptr(mu), _ptr(alpha), _ptr(Goff), _ptr(G), _ptr(dG),
+                            _stream(stream)), "cos_build_g0")
+
+
+def chain_mu_shift(nconf, n, nmat, Goff, G_bar, dG, stub_bar, nstub, U, mu_bar, alpha_bar, stream=None):
+    _check(lib.cos_chain_mu_shift(int(nconf), _ptr(n), int(nmat), _ptr(Goff), _ptr(G_bar), _ptr(dG),
+                                  _ptr(stub_bar), int(nstub), float(U), _ptr(mu_bar), _ptr(alpha_bar),
+                                  _stream(stream)), "cos_chain_mu_shift")

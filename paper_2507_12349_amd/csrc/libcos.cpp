@@ -1,0 +1,505 @@
+// libcos host side: argument validation, state tables (plans), batch handles,
+// workspace and kernel launches behind the C ABI of include/libcos.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "cos_internal.hpp"
+
+using namespace libcos;
+
+namespace {
+
+thread_local std::string g_err;
+
+cos_status fail(cos_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+cos_status fail(cos_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(COS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));           \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Host plan: the state tables for one order n (identical for every
+// configuration and flavour).  Rows are ordered by level, then mask code,
+// then head slot; masks by level then code.
+// ---------------------------------------------------------------------------
+struct HostPlan {
+    int n = 0;
+    std::vector<int32_t> rowbase;   // [3^n]
+    std::vector<uint32_t> minfo;    // [3^n]
+    std::vector<int2> rows;
+    std::vector<int32_t> masks;
+    std::vector<int4> levels;       // [2n + 2]
+    int32_t max_rows = 0, max_masks = 0;
+    int64_t states = 0, ext = 0, closes = 0, shift_edges = 0;
+};
+
+void build_host_plan(int n, HostPlan &P) {
+    const int N3 = pow3(n);
+    P.n = n;
+    P.rowbase.assign(N3, -1);
+    P.minfo.assign(N3, 0);
+    std::vector<std::vector<int32_t>> bylevel(2 * n + 2);
+    for (int code = 0; code < N3; ++code) {
+        uint32_t ones = 0, twos = 0;
+        int c = code, lvl = 0;
+        for (int k = 0; k < n; ++k) {
+            int d = c % 3;
+            c /= 3;
+            if (d == 1) ones |= 1u << k;
+            if (d == 2) twos |= 1u << k;
+            lvl += d;
+        }
+        P.minfo[code] = ones | (twos << 16);
+        if (!((ones | twos) & 1u)) continue;   // vertex 0 is always visited
+        bylevel[lvl].push_back(code);
+    }
+    P.levels.assign(2 * n + 2, make_int4(0, 0, 0, 0));
+    for (int l = 1; l <= 2 * n; ++l) {
+        int4 L;
+        L.x = (int)P.rows.size();
+        L.z = (int)P.masks.size();
+        int r = 0, mi = 0;
+        for (int code : bylevel[l]) {
+            const uint32_t ones = P.minfo[code] & 0xffffu, twos = P.minfo[code] >> 16;
+            P.rowbase[code] = r;
+            P.masks.push_back(code);
+            int nopen = 0, nzero = 0;
+            for (int k = 0; k < n; ++k) {
+                if (!((twos >> k) & 1u)) ++nopen;
+                if (!(((ones | twos) >> k) & 1u)) ++nzero;
+            }
+            // heads in slot order: 0, then h >= 1 with m_h = 2 (only when m_0 = 2)
+            std::vector<int> heads{0};
+            if (twos & 1u)
+                for (int h = 1; h < n; ++h)
+                    if ((twos >> h) & 1u) heads.push_back(h);
+            for (int u : heads) {
+                P.rows.push_back(make_int2((code << 4) | u, mi));
+                const int cnt = __builtin_popcount(current_set(u, ones, twos));
+                P.states += cnt;
+                P.ext += (int64_t)cnt * nopen;
+                P.shift_edges += (int64_t)cnt * nzero;
+                ++r;
+            }
+            ++mi;
+        }
+        L.y = r;
+        L.w = mi;
+        P.levels[l] = L;
+        P.max_rows = std::max(P.max_rows, r);
+        P.max_masks = std::max(P.max_masks, mi);
+    }
+    P.closes = P.states;
+    P.levels[2 * n + 1] = make_int4((int)P.rows.size(), 0, (int)P.masks.size(), 0);
+}
+
+struct DevTables {
+    DevPlan dp{};
+    void *mem = nullptr;
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, int>, std::shared_ptr<HostPlan>> g_host;   // (n, 0)
+std::map<std::pair<int, int>, DevTables> g_dev;                    // (device, n)
+
+std::shared_ptr<HostPlan> host_plan(int n) {
+    auto key = std::make_pair(n, 0);
+    auto it = g_host.find(key);
+    if (it != g_host.end()) return it->second;
+    auto p = std::make_shared<HostPlan>();
+    build_host_plan(n, *p);
+    g_host[key] = p;
+    return p;
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+cos_status device_plan(int dev, int n, DevPlan *out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, n);
+    auto it = g_dev.find(key);
+    if (it != g_dev.end()) {
+        *out = it->second.dp;
+        return COS_OK;
+    }
+    auto hp = host_plan(n);
+    const size_t s1 = align_up(hp->rowbase.size() * 4), s2 = align_up(hp->minfo.size() * 4),
+                 s3 = align_up(hp->rows.size() * sizeof(int2)), s4 = align_up(hp->masks.size() * 4),
+                 s5 = align_up(hp->levels.size() * sizeof(int4));
+    char *mem = nullptr;
+    if (hipMalloc((void **)&mem, s1 + s2 + s3 + s4 + s5) != hipSuccess)
+        return fail(COS_ENOMEM, "device allocation of the state tables for n=%d failed", n);
+    hipError_t e = hipSuccess;
+    size_t o = 0;
+    e = e ? e : hipMemcpy(mem + o, hp->rowbase.data(), hp->rowbase.size() * 4, hipMemcpyHostToDevice); o += s1;
+    e = e ? e : hipMemcpy(mem + o, hp->minfo.data(), hp->minfo.size() * 4, hipMemcpyHostToDevice); o += s2;
+    e = e ? e : hipMemcpy(mem + o, hp->rows.data(), hp->rows.size() * sizeof(int2), hipMemcpyHostToDevice); o += s3;
+    e = e ? e : hipMemcpy(mem + o, hp->masks.data(), hp->masks.size() * 4, hipMemcpyHostToDevice); o += s4;
+    e = e ? e : hipMemcpy(mem + o, hp->levels.data(), hp->levels.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(COS_EDEVICE, "upload of the state tables failed: %s", hipGetErrorString(e));
+    }
+    DevTables t;
+    t.mem = mem;
+    o = 0;
+    t.dp.rowbase = (const int32_t *)(mem + o); o += s1;
+    t.dp.minfo = (const uint32_t *)(mem + o); o += s2;
+    t.dp.rows = (const int2 *)(mem + o); o += s3;
+    t.dp.masks = (const int32_t *)(mem + o); o += s4;
+    t.dp.levels = (const int4 *)(mem + o);
+    t.dp.n = n;
+    t.dp.max_rows = hp->max_rows;
+    t.dp.max_masks = hp->max_masks;
+    t.dp.total_rows = (int64_t)hp->rows.size();
+    g_dev[key] = t;
+    *out = t.dp;
+    return COS_OK;
+}
+
+cos_status check_device(int *dev, int *ncu) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
+        return fail(COS_EUNSUPPORTED, "no HIP device available");
+    HIP_TRY(hipGetDevice(dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(COS_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev, prop.gcnArchName);
+    *ncu = prop.multiProcessorCount;
+    return COS_OK;
+}
+
+cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
+    if (variant != COS_UNIFORM && variant != COS_FLAVOUR)
+        return fail(COS_EINVAL, "variant must be COS_UNIFORM (0) or COS_FLAVOUR (1), got %d", variant);
+    if (flags & ~COS_F_STUBS) return fail(COS_EINVAL, "unknown flag bits 0x%x", flags & ~COS_F_STUBS);
+    if (nflav < 1 || nflav > COS_FMAX) return fail(COS_ERANGE, "nflav must be in [1, %d], got %d", COS_FMAX, nflav);
+    return COS_OK;
+}
+
+// waves per workgroup: a multiple of the flavour-slot count (each wave works
+// on one flavour, so G_l stays uniform over the wave)
+int pick_waves(int nfs, int max_waves) {
+    int w = nfs * std::max(1, max_waves / nfs);
+    return std::min(w, std::max(nfs, 1) * std::max(1, 16 / std::max(nfs, 1)));
+}
+
+}  // namespace
+
+struct cos_batch_s {
+    int dev = 0, ncu = 0;
+    int32_t nconf = 0, nflav = 0, variant = 0, flags = 0;
+    int nfs = 1, nmat = 1, nstub = 1;
+    bool uniform_n = true;
+    int nmax = 0;
+    std::vector<int32_t> n_host;
+    DevPlan plans[COS_NMAX + 1]{};
+    int32_t *d_order = nullptr;   // forward schedule (most work first)
+    int32_t *d_counter = nullptr;
+    double *d_ws = nullptr;
+    int64_t ws_per_wg = 0;
+    int grid = 0, block = 256;
+    std::vector<std::pair<int, std::pair<int, int>>> groups;   // order -> [start, count) in d_order
+
+    double *d_adj_ws = nullptr;
+    int64_t adj_ws_per_wg = 0;
+    int adj_grid = 0, adj_block = 256;
+};
+
+extern "C" {
+
+const char *cos_status_string(cos_status s) {
+    switch (s) {
+        case COS_OK: return "ok";
+        case COS_EINVAL: return "invalid argument";
+        case COS_ERANGE: return "argument out of range";
+        case COS_ENOMEM: return "out of memory";
+        case COS_EDEVICE: return "device error";
+        case COS_EUNSUPPORTED: return "unsupported device";
+    }
+    return "unknown status";
+}
+
+const char *cos_last_error(void) { return g_err.c_str(); }
+
+cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
+                           int64_t *shift_edges, int64_t *masks, int64_t *rows) {
+    if (n < 1 || n > COS_NMAX) return fail(COS_ERANGE, "n must be in [1, %d], got %d", COS_NMAX, n);
+    std::shared_ptr<HostPlan> p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        p = host_plan(n);
+    }
+    if (states) *states = p->states;
+    if (extensions) *extensions = p->ext;
+    if (closes) *closes = p->closes;
+    if (shift_edges) *shift_edges = p->shift_edges;
+    if (masks) *masks = (int64_t)p->masks.size();
+    if (rows) *rows = (int64_t)p->rows.size();
+    return COS_OK;
+}
+
+cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int32_t variant,
+                            int32_t flags, cos_batch_t *out) {
+    if (!out) return fail(COS_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nconf < 1) return fail(COS_EINVAL, "nconf must be >= 1, got %d", nconf);
+    if (!n) return fail(COS_EINVAL, "n is NULL");
+    cos_status st = check_common(nflav, variant, flags);
+    if (st) return st;
+    for (int32_t c = 0; c < nconf; ++c)
+        if (n[c] < 1 || n[c] > COS_NMAX)
+            return fail(COS_ERANGE, "n[%d] = %d outside [1, %d]", c, n[c], COS_NMAX);
+    int dev = 0, ncu = 0;
+    if ((st = check_device(&dev, &ncu))) return st;
+
+    struct Del { void operator()(cos_batch_s *p) const { cos_batch_destroy(p); } };
+    std::unique_ptr<cos_batch_s, Del> b(new cos_batch_s());
+    b->dev = dev;
+    b->ncu = ncu;
+    b->nconf = nconf;
+    b->nflav = nflav;
+    b->variant = variant;
+    b->flags = flags;
+    b->nfs = variant == COS_FLAVOUR ? nflav : 1;
+    b->nmat = b->nfs;
+    b->nstub = b->nfs;
+    b->n_host.assign(n, n + nconf);
+    bool seen[COS_NMAX + 1] = {false};
+    for (int c = 0; c < nconf; ++c) seen[n[c]] = true;
+    for (int k = 1; k <= COS_NMAX; ++k)
+        if (seen[k]) {
+            if ((st = device_plan(dev, k, &b->plans[k]))) return st;
+            b->nmax = k;
+        }
+    b->uniform_n = std::all_of(n, n + nconf, [&](int32_t x) { return x == n[0]; });
+
+    // schedule: configurations grouped by order, largest order first; each
+    // group is one persistent launch whose workgroups pull from a queue
+    std::vector<int32_t> order(nconf);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return n[a] > n[c]; });
+    for (int i = 0; i < nconf;) {
+        int j = i;
+        while (j < nconf && n[order[j]] == n[order[i]]) ++j;
+        b->groups.push_back({n[order[i]], {i, j - i}});
+        i = j;
+    }
+    const int waves = pick_waves(b->nfs, 4);
+    b->block = 64 * waves;
+    int64_t ws = 0;
+    for (int k = 1; k <= COS_NMAX; ++k)
+        if (seen[k]) ws = std::max(ws, fwd_ws_doubles(b->plans[k], b->nfs));
+    b->ws_per_wg = (ws + 31) & ~(int64_t)31;
+    const int per_cu = std::max(1, 16 / waves);
+    b->grid = std::max(1, std::min<int>(nconf, ncu * per_cu));
+    if (hipMalloc((void **)&b->d_order, sizeof(int32_t) * nconf) != hipSuccess ||
+        hipMalloc((void **)&b->d_counter, 256) != hipSuccess ||
+        hipMalloc((void **)&b->d_ws, sizeof(double) * (size_t)b->ws_per_wg * b->grid) != hipSuccess)
+        return fail(COS_ENOMEM, "workspace allocation failed");
+    HIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nconf, hipMemcpyHostToDevice));
+    *out = b.release();
+    return COS_OK;
+}
+
+cos_status cos_batch_destroy(cos_batch_t b) {
+    if (!b) return COS_OK;
+    (void)hipFree(b->d_order);
+    (void)hipFree(b->d_counter);
+    (void)hipFree(b->d_ws);
+    (void)hipFree(b->d_adj_ws);
+    delete b;
+    return COS_OK;
+}
+
+static cos_status check_batch_ptrs(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
+                                   const double *d_stub) {
+    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    if (!d_G) return fail(COS_EINVAL, "d_G is NULL");
+    if (!d_Goff && !b->uniform_n) return fail(COS_EINVAL, "d_Goff is required when the orders differ");
+    if ((b->flags & COS_F_STUBS) && !d_stub) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub is NULL");
+    return COS_OK;
+}
+
+cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
+                                     const double *d_stub, double cycle_weight, double *d_out,
+                                     void *stream) {
+    cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
+    if (st) return st;
+    if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
+    // one persistent launch per distinct order (a uniform batch is one launch)
+    for (auto &g : b->groups) {
+        FwdArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.plan = b->plans[g.first];
+        a.order = b->d_order + g.second.first;
+        a.G = d_G;
+        a.Goff = d_Goff;
+        a.stub = (b->flags & COS_F_STUBS) ? d_stub : nullptr;
+        a.out = d_out;
+        a.ws = b->d_ws;
+        a.counter = b->d_counter;
+        a.ws_per_wg = b->ws_per_wg;
+        a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
+        a.nconf = g.second.second;
+        a.nfs = b->nfs;
+        a.nmat = b->nmat;
+        a.nstub = b->nstub;
+        a.variant = b->variant;
+        a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
+        const int grid = std::max(1, std::min(b->grid, a.nconf));
+        HIP_TRY(launch_forward(a, grid, b->block, (hipStream_t)stream));
+    }
+    return COS_OK;
+}
+
+static cos_status prepare_adjoint(cos_batch_t b) {
+    if (b->d_adj_ws) return COS_OK;
+    const int waves = std::max(b->nfs, b->nfs * std::max(1, 4 / b->nfs));
+    b->adj_block = 64 * waves;
+    int64_t ws = 0;
+    int maxcnt = 0;
+    for (auto &g : b->groups) {
+        ws = std::max(ws, adj_ws_doubles(b->plans[g.first], b->nfs));
+        maxcnt = std::max(maxcnt, g.second.second);
+    }
+    b->adj_ws_per_wg = (ws + 31) & ~(int64_t)31;
+    b->adj_grid = std::max(1, std::min(maxcnt, b->ncu * 2));
+    if (hipMalloc((void **)&b->d_adj_ws, sizeof(double) * (size_t)b->adj_ws_per_wg * b->adj_grid) != hipSuccess) {
+        b->d_adj_ws = nullptr;
+        return fail(COS_ENOMEM, "adjoint workspace allocation failed (%.1f MB)",
+                    8.0 * b->adj_ws_per_wg * b->adj_grid / 1e6);
+    }
+    return COS_OK;
+}
+
+cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
+                                     const double *d_stub, double cycle_weight,
+                                     const double *d_out_bar, double *d_out, double *d_G_bar,
+                                     double *d_stub_bar, void *stream) {
+    cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
+    if (st) return st;
+    if (!d_out_bar || !d_G_bar) return fail(COS_EINVAL, "d_out_bar and d_G_bar are required");
+    if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
+    if ((st = prepare_adjoint(b))) return st;
+    for (auto &g : b->groups) {
+        AdjArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.plan = b->plans[g.first];
+        a.order = b->d_order + g.second.first;
+        a.G = d_G;
+        a.Goff = d_Goff;
+        a.stub = (b->flags & COS_F_STUBS) ? d_stub : nullptr;
+        a.out_bar = d_out_bar;
+        a.out = d_out;
+        a.G_bar = d_G_bar;
+        a.stub_bar = (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr;
+        a.ws = b->d_adj_ws;
+        a.counter = b->d_counter;
+        a.ws_per_wg = b->adj_ws_per_wg;
+        a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
+        a.nconf = g.second.second;
+        a.nfs = b->nfs;
+        a.nmat = b->nmat;
+        a.nstub = b->nstub;
+        a.variant = b->variant;
+        a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
+        const int grid = std::max(1, std::min(b->adj_grid, a.nconf));
+        HIP_TRY(launch_adjoint(a, grid, b->adj_block, (hipStream_t)stream));
+    }
+    return COS_OK;
+}
+
+cos_status cos_connected_sum(int32_t n, int32_t nflav, int32_t variant, int32_t flags, const double *G,
+                             const double *stub, double cycle_weight, double *out) {
+    if (!G || !out) return fail(COS_EINVAL, "G and out are required");
+    cos_status st = check_common(nflav, variant, flags);
+    if (st) return st;
+    if (n < 1 || n > COS_NMAX) return fail(COS_ERANGE, "n must be in [1, %d], got %d", COS_NMAX, n);
+    if ((flags & COS_F_STUBS) && !stub) return fail(COS_EINVAL, "COS_F_STUBS set but stub is NULL");
+    cos_batch_t b = nullptr;
+    if ((st = cos_batch_create(1, &n, nflav, variant, flags, &b))) return st;
+    const size_t ng = (size_t)b->nmat * n * n;
+    double *d = nullptr;
+    if (hipMalloc((void **)&d, sizeof(double) * (ng + COS_FMAX + 1)) != hipSuccess) {
+        cos_batch_destroy(b);
+        return fail(COS_ENOMEM, "device allocation failed");
+    }
+    hipError_t e = hipMemcpy(d, G, sizeof(double) * ng, hipMemcpyHostToDevice);
+    if (!e && (flags & COS_F_STUBS)) e = hipMemcpy(d + ng, stub, sizeof(double) * b->nstub, hipMemcpyHostToDevice);
+    if (!e) {
+        st = cos_connected_sum_batched(b, d, nullptr, d + ng, cycle_weight, d + ng + COS_FMAX, nullptr);
+        if (!st) e = hipMemcpy(out, d + ng + COS_FMAX, sizeof(double), hipMemcpyDeviceToHost);
+    }
+    (void)hipFree(d);
+    cos_batch_destroy(b);
+    if (e) return fail(COS_EDEVICE, "HIP error: %s", hipGetErrorString(e));
+    return st;
+}
+
+cos_status cos_build_g0(int32_t nconf, const int32_t *d_n, const int64_t *d_voff, const int32_t *d_sites,
+                        const double *d_tau, int32_t L, double t, double beta, int32_t nmat, const double *mu,
+                        const double *alpha, const int64_t *d_Goff, double *d_G, double *d_dG, void *stream) {
+    if (nconf < 1) return fail(COS_EINVAL, "nconf must be >= 1");
+    if (!d_n || !d_voff || !d_sites || !d_tau || !d_Goff || !d_G || !mu || !alpha)
+        return fail(COS_EINVAL, "null pointer argument");
+    if (L < 1 || L > 32) return fail(COS_ERANGE, "L must be in [1, 32], got %d", L);
+    if (nmat < 1 || nmat > COS_FMAX) return fail(COS_ERANGE, "nmat must be in [1, %d]", COS_FMAX);
+    if (!(beta > 0.0)) return fail(COS_ERANGE, "beta must be positive");
+    HIP_TRY(launch_g0(nconf, d_n, d_voff, d_sites, d_tau, L, t, beta, nmat, mu, alpha, d_Goff, d_G, d_dG,
+                      (hipStream_t)stream));
+    return COS_OK;
+}
+
+cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat, const int64_t *d_Goff,
+                              const double *d_G_bar, const double *d_dG, const double *d_stub_bar,
+                              int32_t nstub, double U, double *d_mu_bar, double *d_alpha_bar, void *stream) {
+    if (nconf < 1) return fail(COS_EINVAL, "nconf must be >= 1");
+    if (!d_n || !d_Goff || !d_G_bar || !d_dG || !d_mu_bar || !d_alpha_bar)
+        return fail(COS_EINVAL, "null pointer argument");
+    if (nmat < 1 || nmat > COS_FMAX) return fail(COS_ERANGE, "nmat must be in [1, %d]", COS_FMAX);
+    if (d_stub_bar && nstub != 1 && nstub != nmat) return fail(COS_EINVAL, "nstub must be 1 or nmat");
+    if (d_stub_bar && U == 0.0) return fail(COS_EINVAL, "U must be nonzero");
+    HIP_TRY(launch_chain(nconf, d_n, nmat, d_Goff, d_G_bar, d_dG, d_stub_bar, nstub, U, d_mu_bar, d_alpha_bar,
+                         (hipStream_t)stream));
+    return COS_OK;
+}
+
+cos_status cos_release(void) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_dev) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(kv.first.first);
+        (void)hipFree(kv.second.mem);
+        (void)hipSetDevice(cur);
+    }
+    g_dev.clear();
+    g_host.clear();
+    return COS_OK;
+}
+
+}  // extern "C"

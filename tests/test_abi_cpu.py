@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function the public header declares, plans the state space exactly, and
+rejects bad arguments before touching a device."""
+import ctypes
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libcos.h")
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_2507_12349_amd import _binding
+    return _binding
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(cos_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported(B):
+    names = _declared()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(B.lib, name), name
+    assert sorted(B.EXPORTED) == names
+
+
+@pytest.mark.parametrize("n", range(1, 13))
+def test_plan_counts_match_golden(B, n):
+    with open(os.path.join(ROOT, "tests", "golden", "plan_counts.json")) as f:
+        g = json.load(f)["counts"][str(n)]
+    c = B.plan_counts(n)
+    assert (c["states"], c["ext"], c["closes"], c["stub_edges"], c["masks"]) == \
+        (g["states"], g["ext"], g["closes"], g["stub_edges"], g["masks"])
+    # rows: one per (mask, head); head 0 for every mask, head h >= 1 when m_0 = m_h = 2
+    assert c["rows"] == 2 * 3 ** (n - 1) + (n - 1) * 3 ** max(n - 2, 0) * (1 if n >= 2 else 0)
+
+
+def _st(B, code):
+    return B.lib.cos_status_string(code).decode()
+
+
+def test_argument_validation_without_device(B):
+    lib = B.lib
+    v = ctypes.c_int64()
+    assert lib.cos_plan_counts(0, ctypes.byref(v), None, None, None, None, None) == -2
+    assert lib.cos_plan_counts(13, ctypes.byref(v), None, None, None, None, None) == -2
+    h = ctypes.c_void_p()
+    n = np.array([4, 5], dtype=np.int32)
+    assert lib.cos_batch_create(0, n.ctypes.data, 2, 0, 0, ctypes.byref(h)) == -1
+    assert lib.cos_batch_create(2, None, 2, 0, 0, ctypes.byref(h)) == -1
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 0, None) == -1
+    assert lib.cos_batch_create(2, n.ctypes.data, 0, 0, 0, ctypes.byref(h)) == -2
+    assert lib.cos_batch_create(2, n.ctypes.data, 17, 0, 0, ctypes.byref(h)) == -2
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 7, 0, ctypes.byref(h)) == -1
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 8, ctypes.byref(h)) == -1
+    bad = np.array([4, 13], dtype=np.int32)
+    assert lib.cos_batch_create(2, bad.ctypes.data, 2, 0, 0, ctypes.byref(h)) == -2
+    assert "n[1] = 13" in lib.cos_last_error().decode()
+    G = np.eye(3)
+    out = ctypes.c_double()
+    assert lib.cos_connected_sum(3, 2, 0, 0, None, None, -1.0, ctypes.byref(out)) == -1
+    assert lib.cos_connected_sum(3, 2, 0, 1, G.ctypes.data, None, -1.0, ctypes.byref(out)) == -1
+    assert lib.cos_connected_sum(0, 2, 0, 0, G.ctypes.data, None, -1.0, ctypes.byref(out)) == -2
+    assert lib.cos_connected_sum_batched(None, None, None, None, -1.0, None, None) == -1
+    assert lib.cos_build_g0(1, 1, 1, 1, 1, 0, 1.0, 1.0, 1, G.ctypes.data, G.ctypes.data, 1, 1, None, None) == -2
+    assert lib.cos_chain_mu_shift(0, None, 1, None, None, None, None, 1, 1.0, None, None, None) == -1
+    assert _st(B, 0) == "ok" and _st(B, -2) == "argument out of range"
+
+
+def test_binding_raises_typed_errors(B):
+    with pytest.raises(B.CosError) as e:
+        B.plan_counts(20)
+    assert e.value.status == -2
+
+
+def test_no_gpu_reports_unsupported(B):
+    """Without a usable gfx950 device the library says so instead of computing
+    anything elsewhere (skipped where a GPU is present)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(B.CosError) as e:
+        B.connected_sum_host(np.eye(3), 2)
+    assert e.value.status in (-5, -4)
