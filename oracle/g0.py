@@ -14,7 +14,8 @@ real-space matrix between vertices (r_k, tau_k) and (r_l, tau_l) is
 
 ``dG_dxi`` is the derivative of that matrix when xi_s(k) moves by the same
 amount at every k (d/dmu_s = -d/dxi, d/dalpha_s = +d/dxi).  Plain numpy,
-float64, direct formulas.
+float64, direct formulas (1 - nF evaluated as 1/(1 + exp(-beta xi)) so that
+no cancellation occurs for xi < 0).
 """
 from __future__ import annotations
 
@@ -42,7 +43,8 @@ def build_g0(L, t, beta, mu, alpha, sites, tau):
     dG = np.zeros((nf, n, n))
     for s in range(nf):
         xi, kx, ky = dispersion(L, t, mu[s], alpha[s])
-        nF = 1.0 / (np.exp(beta * xi) + 1.0)
+        nF = 1.0 / (np.exp(beta * xi) + 1.0)           # occupation
+        hF = 1.0 / (1.0 + np.exp(-beta * xi))          # 1 - nF, written without cancellation
         for a in range(n):
             for b in range(n):
                 dx = sites[a, 0] - sites[b, 0]
@@ -50,7 +52,7 @@ def build_g0(L, t, beta, mu, alpha, sites, tau):
                 d = tau[a] - tau[b]
                 ph = np.cos(kx * dx + ky * dy)
                 if d > 0:
-                    gk = -np.exp(-xi * d) * (1.0 - nF)
+                    gk = -np.exp(-xi * d) * hF
                     dgk = gk * (beta * nF - d)
                 else:
                     gk = np.exp(-xi * d) * nF

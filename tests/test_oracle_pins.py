@@ -265,3 +265,32 @@ def test_g0_pins():
     nF = 1 / (np.exp(beta * xi) + 1)
     assert np.isclose(a[0, 0, 1], -np.exp(-xi * 0.5) * (1 - nF), rtol=1e-14)
     assert np.isclose(a[0, 1, 0], np.exp(xi * 0.5) * nF, rtol=1e-14)
+
+
+def test_g0_against_high_precision():
+    """The oracle's float64 propagator against the defining sum evaluated with
+    40-digit arithmetic (mpmath), at beta = 5 where nF is within 1e-9 of 1 for
+    the lowest band states (the regime where 1 - nF must not cancel)."""
+    import mpmath as mp
+    from oracle import g0
+    mp.mp.dps = 40
+    L, t, beta, al = 8, 1.0, 5.0, 0.19
+    sites = np.array([[0, 0], [3, 5]])
+    tau = np.array([4.9, 0.05])
+    G, _ = g0.build_g0(L, t, beta, np.array([0.0]), np.array([al]), sites, tau)
+
+    def exact(dx, dy, d):
+        s = mp.mpf(0)
+        for mx in range(L):
+            for my in range(L):
+                kx, ky = 2 * mp.pi * mx / L, 2 * mp.pi * my / L
+                xi = -2 * t * (mp.cos(kx) + mp.cos(ky)) + mp.mpf(al)
+                nF = 1 / (mp.exp(beta * xi) + 1)
+                g = -mp.exp(-xi * d) * (1 - nF) if d > 0 else mp.exp(-xi * d) * nF
+                s += mp.cos(kx * dx + ky * dy) * g
+        return s / (L * L)
+
+    for a in range(2):
+        for b in range(2):
+            r = exact(int(sites[a, 0] - sites[b, 0]), int(sites[a, 1] - sites[b, 1]), mp.mpf(tau[a]) - mp.mpf(tau[b]))
+            assert abs(G[0, a, b] - float(r)) <= 4e-16 * max(1.0, abs(float(r))), (a, b)
