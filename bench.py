@@ -1,0 +1,242 @@
+"""Benchmark: connected-sum configurations per second at n = 10, SU(4), FP64.
+
+One step = the whole hot path over one batch of 2048 synthetic vertex
+configurations (8x8 lattice, beta = 4, mu = -0.5, uniform SU(4), shifts at
+delta = 0), inputs resident on the GPU:
+  propagators (G0 kernel)  ->  reverse sweep (the forward sum is recomputed
+  inside and S is written)  ->  chain rule to (mu, shift).
+`value` = configurations per second of that step (forward + adjoint).
+Also reported: the batched forward alone (G0 + forward) and the plain form
+(one launch per configuration, forward only) on the same device.
+
+Prints ONE JSON line.  Options: --gpus (only 1 is supported), --steps,
+--warmup, --no-cpu (skip the oracle baseline), --nconf.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64 = 78.6e12           # MI355X FP64 vector peak, FLOP/s
+WORKLOAD = "adjoint"
+
+
+def _kernel_hash():
+    h = hashlib.sha256()
+    for f in ("cos_kernels.hip", "libcos.cpp", "cos_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2507_12349_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        t = json.load(f)
+    if t.get("kernel_sources_sha") != _kernel_hash():
+        return None
+    e = t.get("kernels", {}).get(kernel)
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def cpu_baseline(d, nsample, threads):
+    """The oracle (C, float64) on host cores: propagators (numpy), reverse sweep
+    with the forward sum (oracle DP), chain rule; one configuration per task."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from oracle import g0
+    w = d.workload
+    oracle.build(force=False)
+
+    def one(c):
+        sites, tau = d.config(c)
+        G, dG = g0.build_g0(w.L, w.t, w.beta, np.array(w.mu[:1]), np.zeros(1), sites, tau)
+        S, Gb, sb = oracle.dp_adjoint(G[0], w.nflav, 0, np.zeros(1), precision="d")
+        xb = float(np.sum(Gb * dG[0]))
+        return S, -xb, (xb + sb[0] / w.U) / w.nflav
+
+    one(0)
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, range(nsample)))
+    dt = time.perf_counter() - t0
+    return nsample / dt, dt
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--nconf", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the configurations are independent and a "
+              "multi-GPU run would shard them with no collective on the hot path; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2507_12349_amd import _binding as B
+    from paper_2507_12349_amd.autograd import Geometry
+    from paper_2507_12349_amd.workloads import draw
+
+    d = draw(WORKLOAD, nconf=args.nconf or None)
+    w = d.workload
+    nconf = int(d.n.size)
+    n = int(d.n[0])
+    dev = torch.device("cuda:0")
+    geo = Geometry(d, 1, dev)
+    mu, alpha = np.array(w.mu[:1]), np.zeros(1)
+    G = torch.empty(geo.total, dtype=torch.float64, device=dev)
+    dG = torch.empty_like(G)
+    Gb = torch.empty_like(G)
+    stub = torch.zeros((nconf, 1), dtype=torch.float64, device=dev)
+    sb = torch.empty_like(stub)
+    S = torch.empty(nconf, dtype=torch.float64, device=dev)
+    obar = torch.ones(nconf, dtype=torch.float64, device=dev)
+    mub = torch.empty(nconf, dtype=torch.float64, device=dev)
+    alb = torch.empty(nconf, dtype=torch.float64, device=dev)
+    batch = B.Batch(d.n, w.nflav, 0, stubs=True)
+    fwd_batch = B.Batch(d.n, w.nflav, 0, stubs=False)
+    stream = torch.cuda.current_stream()
+
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in ("g0", "adj", "chain")}
+    acc = {k: 0.0 for k in ev}
+
+    def step(timed):
+        e = ev["g0"]
+        if timed: e[0].record(stream)
+        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
+        if timed: e[1].record(stream); ev["adj"][0].record(stream)
+        batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
+        if timed: ev["adj"][1].record(stream); ev["chain"][0].record(stream)
+        B.chain_mu_shift(nconf, geo.n, 1, geo.Goff, Gb, dG, sb, 1, w.U, mub, alb, stream)
+        if timed: ev["chain"][1].record(stream)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()   # per-step sync so the per-kernel events can be read
+        for k, (a, b) in ev.items():
+            acc[k] += a.elapsed_time(b)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    value = nconf / (wall / args.steps)
+
+    # batched forward alone (G0 + forward) and the plain one-launch-per-config form
+    def fwd_batched():
+        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
+        fwd_batch.forward(G, geo.Goff, None, -1.0, S, stream)
+
+    for _ in range(3):
+        fwd_batched()
+    torch.cuda.synchronize()
+    fe0, fe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fk0, fk1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps // 2)
+    fwd_kernel_ms = 0.0
+    fe0.record(stream)
+    for _ in range(reps):
+        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
+        fk0.record(stream)
+        fwd_batch.forward(G, geo.Goff, None, -1.0, S, stream)
+        fk1.record(stream)
+        fk1.synchronize()
+        fwd_kernel_ms += fk0.elapsed_time(fk1)
+    fe1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = fe0.elapsed_time(fe1) / reps
+    fwd_kernel_ms /= reps
+    S_batched = S.clone()
+
+    one = B.Batch([n], w.nflav, 0, stubs=False)
+    Sp = torch.empty_like(S)
+    nn = n * n
+    goff = geo.Goff_host
+    for c in range(min(nconf, 32)):
+        one.forward(G[int(goff[c]):int(goff[c]) + nn], None, None, -1.0, Sp[c:c + 1], stream)
+    torch.cuda.synchronize()
+    pe0, pe1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pe0.record(stream)
+    for c in range(nconf):
+        one.forward(G[int(goff[c]):int(goff[c]) + nn], None, None, -1.0, Sp[c:c + 1], stream)
+    pe1.record(stream)
+    torch.cuda.synchronize()
+    plain_ms = pe0.elapsed_time(pe1)
+    plain_equal = bool(torch.equal(Sp, S_batched))
+
+    # roofline of the dominant kernel (reverse sweep): algorithmic FLOP per
+    # configuration = 6 (E + C): forward recompute 2 (E + C), reverse 4 (E + C)
+    pc = B.plan_counts(n)
+    flop_fwd = 2.0 * (pc["ext"] + pc["closes"])
+    flop_adj = 3.0 * flop_fwd
+    adj_ms = acc["adj"] / args.steps
+    achieved = flop_adj * nconf / (adj_ms * 1e-3)
+    traffic = _traffic("adjoint_kernel<10,256>")
+
+    cpu = None
+    if not args.no_cpu:
+        threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
+        rate, dt = cpu_baseline(d, args.cpu_sample, threads)
+        cpu = {"value": rate, "unit": "configs/s", "cores": threads, "kind": "oracle",
+               "sample": "%d configs of the same workload (propagators, float64 DP forward + reverse sweep, "
+                         "chain rule), one config per thread, %.1f s wall" % (args.cpu_sample, dt)}
+
+    rec = {
+        "metric": "connected-sum configs/sec at n=10 SU(4) FP64 (batched vs plain; fwd+adjoint)",
+        "value": value,
+        "unit": "configs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded uniform sites and times, 8x8 lattice)",
+        "config": {"workload": "adjoint: 8x8 lattice, beta=4, mu=-0.5, SU(4) uniform, n=10, "
+                               "%d configs, forward + reverse sweep + chain rule to mu and shift" % nconf,
+                   "n": n, "nflav": w.nflav, "nconf": nconf, "parallelism": "single GPU, persistent batched launch"},
+        "breakdown_ms": {"g0": acc["g0"] / args.steps, "adjoint_incl_forward": adj_ms,
+                         "chain": acc["chain"] / args.steps},
+        "forward_batched_configs_per_s": nconf / (fwd_ms * 1e-3),
+        "forward_kernel_ms": fwd_kernel_ms,
+        "forward_plain_configs_per_s": nconf / (plain_ms * 1e-3),
+        "batched_over_plain": (nconf / (fwd_ms * 1e-3)) / (nconf / (plain_ms * 1e-3)),
+        "plain_equals_batched_bitwise": plain_equal,
+        "roofline": {"bound": "alu", "kernel": "adjoint_kernel<10,256> (reverse sweep with forward recompute)",
+                     "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64, "traffic": traffic,
+                     "flop_per_config": flop_adj,
+                     "forward_kernel_tflops": flop_fwd * nconf / (fwd_kernel_ms * 1e-3) / 1e12},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

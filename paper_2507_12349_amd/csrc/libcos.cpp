@@ -136,6 +136,10 @@ std::shared_ptr<HostPlan> host_plan(int n) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// upper bound on a batch's workspace (bytes); larger orders get fewer
+// concurrent workgroups instead of more memory
+constexpr int64_t kWorkspaceCap = (int64_t)24 << 30;
+
 cos_status device_plan(int dev, int n, DevPlan *out) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto key = std::make_pair(dev, n);
@@ -220,13 +224,15 @@ struct cos_batch_s {
     int32_t *d_order = nullptr;   // forward schedule (most work first)
     int32_t *d_counter = nullptr;
     double *d_ws = nullptr;
-    int64_t ws_per_wg = 0;
+    std::vector<int64_t> fwd_ws;   // per group: doubles per workgroup
+    std::vector<int> fwd_grid;     // per group: workgroups
     int grid = 0, block = 256;
     std::vector<std::pair<int, std::pair<int, int>>> groups;   // order -> [start, count) in d_order
 
     double *d_adj_ws = nullptr;
-    int64_t adj_ws_per_wg = 0;
-    int adj_grid = 0, adj_block = 256;
+    std::vector<int64_t> adj_ws;
+    std::vector<int> adj_grid;
+    int adj_block = 256;
 };
 
 extern "C" {
@@ -310,16 +316,23 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
     }
     const int waves = pick_waves(b->nfs, 4);
     b->block = 64 * waves;
-    int64_t ws = 0;
-    for (int k = 1; k <= COS_NMAX; ++k)
-        if (seen[k]) ws = std::max(ws, fwd_ws_doubles(b->plans[k], b->nfs));
-    b->ws_per_wg = (ws + 31) & ~(int64_t)31;
     const int per_cu = std::max(1, 16 / waves);
     b->grid = std::max(1, std::min<int>(nconf, ncu * per_cu));
+    // groups run one after another and share the workspace; each group gets
+    // as many workgroups as it can use, capped so the workspace stays bounded
+    int64_t total = 0;
+    for (auto &g : b->groups) {
+        const int64_t ws = (fwd_ws_doubles(b->plans[g.first], b->nfs) + 31) & ~(int64_t)31;
+        const int64_t cap = std::max<int64_t>(1, kWorkspaceCap / (8 * ws));
+        const int gg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)b->grid, (int64_t)g.second.second, cap}));
+        b->fwd_ws.push_back(ws);
+        b->fwd_grid.push_back(gg);
+        total = std::max(total, ws * gg);
+    }
     if (hipMalloc((void **)&b->d_order, sizeof(int32_t) * nconf) != hipSuccess ||
         hipMalloc((void **)&b->d_counter, 256) != hipSuccess ||
-        hipMalloc((void **)&b->d_ws, sizeof(double) * (size_t)b->ws_per_wg * b->grid) != hipSuccess)
-        return fail(COS_ENOMEM, "workspace allocation failed");
+        hipMalloc((void **)&b->d_ws, sizeof(double) * (size_t)total) != hipSuccess)
+        return fail(COS_ENOMEM, "workspace allocation failed (%.1f MB)", 8.0 * total / 1e6);
     HIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nconf, hipMemcpyHostToDevice));
     *out = b.release();
     return COS_OK;
@@ -351,7 +364,8 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
     if (st) return st;
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
     // one persistent launch per distinct order (a uniform batch is one launch)
-    for (auto &g : b->groups) {
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const auto &g = b->groups[gi];
         FwdArgs a;
         std::memset(&a, 0, sizeof(a));
         a.plan = b->plans[g.first];
@@ -362,7 +376,7 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
         a.out = d_out;
         a.ws = b->d_ws;
         a.counter = b->d_counter;
-        a.ws_per_wg = b->ws_per_wg;
+        a.ws_per_wg = b->fwd_ws[gi];
         a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
         a.nconf = g.second.second;
         a.nfs = b->nfs;
@@ -370,8 +384,7 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
         a.nstub = b->nstub;
         a.variant = b->variant;
         a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
-        const int grid = std::max(1, std::min(b->grid, a.nconf));
-        HIP_TRY(launch_forward(a, grid, b->block, (hipStream_t)stream));
+        HIP_TRY(launch_forward(a, b->fwd_grid[gi], b->block, (hipStream_t)stream));
     }
     return COS_OK;
 }
@@ -380,18 +393,20 @@ static cos_status prepare_adjoint(cos_batch_t b) {
     if (b->d_adj_ws) return COS_OK;
     const int waves = std::max(b->nfs, b->nfs * std::max(1, 4 / b->nfs));
     b->adj_block = 64 * waves;
-    int64_t ws = 0;
-    int maxcnt = 0;
+    int64_t total = 0;
     for (auto &g : b->groups) {
-        ws = std::max(ws, adj_ws_doubles(b->plans[g.first], b->nfs));
-        maxcnt = std::max(maxcnt, g.second.second);
+        const int64_t ws = (adj_ws_doubles(b->plans[g.first], b->nfs) + 31) & ~(int64_t)31;
+        const int64_t cap = std::max<int64_t>(1, kWorkspaceCap / (8 * ws));
+        const int gg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)b->ncu * 2, (int64_t)g.second.second, cap}));
+        b->adj_ws.push_back(ws);
+        b->adj_grid.push_back(gg);
+        total = std::max(total, ws * gg);
     }
-    b->adj_ws_per_wg = (ws + 31) & ~(int64_t)31;
-    b->adj_grid = std::max(1, std::min(maxcnt, b->ncu * 2));
-    if (hipMalloc((void **)&b->d_adj_ws, sizeof(double) * (size_t)b->adj_ws_per_wg * b->adj_grid) != hipSuccess) {
+    if (hipMalloc((void **)&b->d_adj_ws, sizeof(double) * (size_t)total) != hipSuccess) {
         b->d_adj_ws = nullptr;
-        return fail(COS_ENOMEM, "adjoint workspace allocation failed (%.1f MB)",
-                    8.0 * b->adj_ws_per_wg * b->adj_grid / 1e6);
+        b->adj_ws.clear();
+        b->adj_grid.clear();
+        return fail(COS_ENOMEM, "adjoint workspace allocation failed (%.1f MB)", 8.0 * total / 1e6);
     }
     return COS_OK;
 }
@@ -405,7 +420,8 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
     if (!d_out_bar || !d_G_bar) return fail(COS_EINVAL, "d_out_bar and d_G_bar are required");
     if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
     if ((st = prepare_adjoint(b))) return st;
-    for (auto &g : b->groups) {
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const auto &g = b->groups[gi];
         AdjArgs a;
         std::memset(&a, 0, sizeof(a));
         a.plan = b->plans[g.first];
@@ -419,7 +435,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
         a.stub_bar = (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr;
         a.ws = b->d_adj_ws;
         a.counter = b->d_counter;
-        a.ws_per_wg = b->adj_ws_per_wg;
+        a.ws_per_wg = b->adj_ws[gi];
         a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
         a.nconf = g.second.second;
         a.nfs = b->nfs;
@@ -427,8 +443,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
         a.nstub = b->nstub;
         a.variant = b->variant;
         a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
-        const int grid = std::max(1, std::min(b->adj_grid, a.nconf));
-        HIP_TRY(launch_adjoint(a, grid, b->adj_block, (hipStream_t)stream));
+        HIP_TRY(launch_adjoint(a, b->adj_grid[gi], b->adj_block, (hipStream_t)stream));
     }
     return COS_OK;
 }

@@ -57,3 +57,58 @@ def oracle_args(M, variant):
 def scale(oracle, M, nf, variant, st, w=-1.0):
     G = np.abs(oracle_args(M, variant))
     return oracle.dp(G, nf, variant, None if st is None else -np.abs(st), abs(w))
+
+
+def workload_params(draw):
+    """(nmat, nflav, variant, mu, alpha, stubs per config or None) of a workload."""
+    w = draw.workload
+    nmat = w.nflav if w.variant == 1 else 1
+    mu = np.asarray(w.mu[:nmat], dtype=np.float64)
+    alpha = np.asarray(draw.delta[:nmat], dtype=np.float64) if w.variant == 1 else np.zeros(1)
+    stubs = None
+    if w.stubs:
+        sig = (draw.delta[:nmat] / w.U) if w.variant == 1 else np.zeros(1)
+        stubs = np.tile(sig, (draw.n.size, 1))
+    return nmat, w.nflav, w.variant, mu, alpha, stubs
+
+
+def gpu_workload(draw, adjoint=False):
+    """Propagators (G0 kernel) and connected sums (forward kernel) of a drawn
+    workload, all on the GPU; returns host copies."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    from paper_2507_12349_amd.autograd import Geometry
+    nmat, nflav, variant, mu, alpha, stubs = workload_params(draw)
+    geo = Geometry(draw, nmat)
+    G = torch.empty(geo.total, dtype=torch.float64, device=geo.device)
+    dG = torch.empty_like(G)
+    B.build_g0(geo.nconf, geo.n, geo.voff, geo.sites, geo.tau, geo.L, geo.t, geo.beta, mu, alpha, geo.Goff, G, dG)
+    b = B.Batch(draw.n, nflav, variant, stubs=stubs is not None)
+    st = None if stubs is None else torch.as_tensor(stubs, device=geo.device)
+    out = torch.full((geo.nconf,), float("nan"), dtype=torch.float64, device=geo.device)
+    b.forward(G, geo.Goff, st, -1.0, out)
+    res = dict(G=G.cpu().numpy(), dG=dG.cpu().numpy(), S=None, Goff=geo.Goff_host, nmat=nmat, nflav=nflav,
+               variant=variant, mu=mu, alpha=alpha, stubs=stubs)
+    torch.cuda.synchronize()
+    res["S"] = out.cpu().numpy()
+    if adjoint:
+        ob = torch.ones(geo.nconf, dtype=torch.float64, device=geo.device)
+        Gb = torch.full_like(G, float("nan"))
+        sb = None if st is None else torch.full_like(st, float("nan"))
+        out2 = torch.full_like(out, float("nan"))
+        b.adjoint(G, geo.Goff, st, -1.0, ob, out2, Gb, sb)
+        mub = torch.empty(geo.nconf * nmat, dtype=torch.float64, device=geo.device)
+        alb = torch.empty_like(mub)
+        B.chain_mu_shift(geo.nconf, geo.n, nmat, geo.Goff, Gb, dG, sb, 1 if st is None else st.shape[1],
+                         draw.workload.U, mub, alb)
+        torch.cuda.synchronize()
+        res.update(S2=out2.cpu().numpy(), Gb=Gb.cpu().numpy(), sb=None if sb is None else sb.cpu().numpy(),
+                   mub=mub.cpu().numpy().reshape(geo.nconf, nmat), alb=alb.cpu().numpy().reshape(geo.nconf, nmat))
+    b.close()
+    return res
+
+
+def config_mats(res, draw, c):
+    n = int(draw.n[c])
+    a = int(res["Goff"][c])
+    return res["G"][a:a + res["nmat"] * n * n].reshape(res["nmat"], n, n)

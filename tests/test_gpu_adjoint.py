@@ -1,0 +1,85 @@
+"""GPU reverse sweep (dS/dG, dS/dsigma) against the oracle's reverse sweep,
+the Euler identity of a degree-2n form, and the chain rule to (mu, shift)
+against central finite differences of the oracle.
+
+Tolerance for gradients: each entry of dS/dG is a sum of products of 2n-1
+entries, so |error| <= 8 n (n + 2) eps * (the same gradient over absolute
+values), taken from the oracle's reverse sweep on |G|, -|sigma|, |w|."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, config_mats, gpu_forward, gpu_workload, oracle_args
+from paper_2507_12349_amd.workloads import draw
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.mark.parametrize("nf,variant,stubs", [(2, 0, False), (4, 0, True), (3, 1, False), (3, 1, True),
+                                              (6, 1, True)])
+def test_random_adjoint(oracle_mod, nf, variant, stubs):
+    announce("adjoint random nf=%d variant=%d stubs=%d" % (nf, variant, stubs))
+    rng = np.random.default_rng(77 + nf + 3 * variant + stubs)
+    orders = [1, 2, 3, 4, 5, 6, 7, 4] if nf <= 4 else [1, 2, 3, 4, 5]
+    nmat = 1 if variant == 0 else nf
+    mats = [rng.normal(size=(nmat, n, n)) for n in orders]
+    sts = rng.normal(size=(len(orders), nmat)) if stubs else None
+    obar = rng.normal(size=len(orders))
+    S, S2, Gb, sb = gpu_forward(mats, nf, variant, sts, adjoint=True, out_bar=obar)
+    assert np.array_equal(S, S2)
+    for i, M in enumerate(mats):
+        n = M.shape[-1]
+        st = None if sts is None else sts[i]
+        _, gref, sref = oracle_mod.dp_adjoint(oracle_args(M, variant), nf, variant, st)
+        _, gabs, sabs = oracle_mod.dp_adjoint(np.abs(oracle_args(M, variant)), nf, variant,
+                                              None if st is None else -np.abs(st), 1.0)
+        tol = 8 * n * (n + 2) * EPS * abs(obar[i])
+        gg = Gb[i][0] if variant == 0 else Gb[i]
+        assert np.all(np.abs(gg - obar[i] * gref) <= tol * np.abs(gabs) + 1e-300), (i, n)
+        if st is not None:
+            assert np.all(np.abs(sb[i] - obar[i] * sref) <= tol * np.abs(sabs) + 1e-300), (i, n)
+
+
+def test_adjoint_workload(oracle_mod):
+    """Adjoint workload (2048 configs, n = 10, SU(4), shifts at delta = 0):
+    full batch forward + reverse on the GPU; sampled configurations against
+    the oracle's reverse sweep, the Euler identity, and finite differences of
+    the oracle in mu and in one flavour's shift."""
+    from oracle import g0
+    announce("adjoint workload 2048 x n=10")
+    d = draw("adjoint")
+    w = d.workload
+    res = gpu_workload(d, adjoint=True)
+    assert np.array_equal(res["S"], res["S2"])
+    assert np.all(np.isfinite(res["Gb"]))
+    rng = np.random.default_rng(55)
+    idx = sorted(rng.choice(d.n.size, size=4, replace=False).tolist())
+    n = 10
+    for c in idx:
+        sites, tau = d.config(c)
+        Go, dGo = g0.build_g0(w.L, w.t, w.beta, res["mu"], res["alpha"], sites, tau)
+        S, gref, sref = oracle_mod.dp_adjoint(Go[0], w.nflav, 0, np.zeros(1))
+        _, gabs, sabs = oracle_mod.dp_adjoint(np.abs(Go[0]), w.nflav, 0, np.zeros(1), 1.0)
+        a = int(res["Goff"][c])
+        gb = res["Gb"][a:a + n * n].reshape(n, n)
+        tol = 8 * n * (n + 2) * EPS
+        assert np.all(np.abs(gb - gref) <= tol * gabs), c
+        assert abs(res["sb"][c, 0] - sref[0]) <= tol * abs(sabs[0]), c
+        Gg = config_mats(res, d, c)[0]
+        euler = np.sum(Gg * gb)        # sigma = 0: the shift term drops
+        sabs_S = oracle_mod.dp(np.abs(Go[0]), w.nflav, 0, None, 1.0)
+        assert abs(euler - 2 * n * res["S"][c]) <= 4 * tol * 2 * n * sabs_S, c
+        # mu: uniform chemical potential of all flavours
+        h = 1e-5
+        Sp = oracle_mod.dp(g0.build_g0(w.L, w.t, w.beta, res["mu"] + h, res["alpha"], sites, tau)[0][0], w.nflav, 0)
+        Sm = oracle_mod.dp(g0.build_g0(w.L, w.t, w.beta, res["mu"] - h, res["alpha"], sites, tau)[0][0], w.nflav, 0)
+        fd_mu = (Sp - Sm) / (2 * h)
+        assert abs(res["mub"][c, 0] - fd_mu) <= 1e-6 * max(abs(fd_mu), 1e-3 * sabs_S), (c, res["mub"][c, 0], fd_mu)
+        # shift of flavour 0 alone (alpha_0 in xi_0 and sigma_0 = alpha_0 / U), flavour-resolved oracle
+        def S_shift(x):
+            Gs = np.stack([g0.build_g0(w.L, w.t, w.beta, res["mu"], np.array([x if l == 0 else 0.0]), sites, tau)[0][0]
+                           for l in range(w.nflav)])
+            return oracle_mod.dp(Gs, w.nflav, 1, np.array([x / w.U] + [0.0] * (w.nflav - 1)))
+        fd_d = (S_shift(h) - S_shift(-h)) / (2 * h)
+        got = res["alb"][c, 0] / w.nflav
+        assert abs(got - fd_d) <= 1e-6 * max(abs(fd_d), 1e-3 * sabs_S), (c, got, fd_d)

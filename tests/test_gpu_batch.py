@@ -1,0 +1,113 @@
+"""Batching: the plain one-configuration-per-launch form and the batched
+persistent form agree bit for bit; an uneven batch equals its per-order
+pieces; a captured HIP graph replays with new inputs like eager calls."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, pack
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    import torch
+    return torch.as_tensor(x, device="cuda:0")
+
+
+def test_plain_equals_batched():
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    from paper_2507_12349_amd.workloads import draw
+    from gpu_util import gpu_workload
+    announce("plain vs batched, 64 configs of the adjoint workload")
+    d = draw("adjoint", nconf=64)
+    res = gpu_workload(d)
+    G = _dev(res["G"])
+    out = torch.full((64,), float("nan"), dtype=torch.float64, device="cuda:0")
+    one = B.Batch([10], 4, 0)
+    for c in range(64):
+        a = int(res["Goff"][c])
+        one.forward(G[a:a + 100], None, None, -1.0, out[c:c + 1])
+    torch.cuda.synchronize()
+    one.close()
+    assert np.array_equal(out.cpu().numpy(), res["S"])
+
+
+def test_uneven_equals_per_order():
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("uneven batch vs per-order batches")
+    rng = np.random.default_rng(3)
+    orders = [5, 9, 3, 9, 7, 5, 11, 3]
+    mats = [rng.normal(size=(2, n, n)) * 0.6 for n in orders]
+    sts = rng.normal(size=(len(orders), 2)) * 0.1
+    flat, off, n = pack(mats)
+    b = B.Batch(n, 2, 1, stubs=True)
+    out = torch.full((len(orders),), float("nan"), dtype=torch.float64, device="cuda:0")
+    b.forward(_dev(flat), _dev(off), _dev(sts), -1.0, out)
+    whole = out.cpu().numpy()
+    for k in sorted(set(orders)):
+        sel = [i for i, x in enumerate(orders) if x == k]
+        f2, o2, n2 = pack([mats[i] for i in sel])
+        b2 = B.Batch(n2, 2, 1, stubs=True)
+        o = torch.full((len(sel),), float("nan"), dtype=torch.float64, device="cuda:0")
+        b2.forward(_dev(f2), _dev(o2), _dev(np.ascontiguousarray(sts[sel])), -1.0, o)
+        assert np.array_equal(o.cpu().numpy(), whole[sel]), k
+        b2.close()
+    b.close()
+
+
+def test_graph_replay_with_new_inputs():
+    """Capture the batched call on a stream; replay it three times, writing new
+    matrices into the captured input buffer between replays (eager work and a
+    synchronisation between replays), and compare each replay with an eager
+    call on the same inputs."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("graph capture / replay")
+    rng = np.random.default_rng(4)
+    nconf, n = 96, 8
+    b = B.Batch([n] * nconf, 4, 0)
+    G = torch.empty(nconf * n * n, dtype=torch.float64, device="cuda:0")
+    out = torch.zeros(nconf, dtype=torch.float64, device="cuda:0")
+    G.copy_(_dev(rng.normal(size=nconf * n * n) * 0.4))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.forward(G, None, None, -1.0, out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.forward(G, None, None, -1.0, out)
+    ref_out = torch.zeros_like(out)
+    for k in range(3):
+        G.copy_(_dev(rng.normal(size=nconf * n * n) * 0.4))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.clone()
+        b.forward(G, None, None, -1.0, ref_out)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref_out), k
+    b.close()
+
+
+def test_autograd_function_matches_adjoint():
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    from paper_2507_12349_amd.autograd import ConnectedSum
+    from gpu_util import gpu_forward
+    announce("autograd ConnectedSum")
+    rng = np.random.default_rng(5)
+    mats = [rng.normal(size=(1, n, n)) for n in (4, 6, 6)]
+    flat, off, n = pack(mats)
+    b = B.Batch(n, 3, 0)
+    G = _dev(flat).requires_grad_(True)
+    S = ConnectedSum.apply(G, None, b, _dev(off), -1.0)
+    w = _dev(np.array([0.5, -1.0, 2.0]))
+    (S * w).sum().backward()
+    S_ref, _, gb, _ = gpu_forward(mats, 3, 0, None, adjoint=True, out_bar=w.cpu().numpy())
+    assert np.array_equal(S.detach().cpu().numpy(), S_ref)
+    assert np.array_equal(G.grad.cpu().numpy(), np.concatenate([x.reshape(-1) for x in gb]))
+    b.close()

@@ -1,0 +1,87 @@
+"""End-to-end parity on the five synthetic workloads: propagators from the
+G0 kernel vs the oracle's numpy builder, and connected sums of the GPU
+pipeline vs the oracle run on the oracle's own propagators.  Full batches run
+on the GPU in the launch configuration the benchmark uses; sampled
+configurations are checked one by one against the oracle (long double).
+
+Tolerance: relative 1e-10, or the FP64 bound 8 n (n + 2) eps S_abs where a
+configuration's cancellation (kappa = S_abs / |S|) makes that the larger."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, config_mats, gpu_workload, oracle_args
+from paper_2507_12349_amd.workloads import draw
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _check_sample(oracle_mod, d, res, idx):
+    from oracle import g0
+    w = d.workload
+    worst = 0.0
+    for c in idx:
+        n = int(d.n[c])
+        sites, tau = d.config(c)
+        Go, _ = g0.build_g0(w.L, w.t, w.beta, res["mu"], res["alpha"], sites, tau)
+        Gg = config_mats(res, d, c)
+        assert np.allclose(Gg, Go, rtol=0, atol=2e-15), (c, np.abs(Gg - Go).max())
+        st = None if res["stubs"] is None else res["stubs"][c]
+        ref = oracle_mod.dp(oracle_args(Go, res["variant"]), res["nflav"], res["variant"], st)
+        sa = oracle_mod.dp(np.abs(oracle_args(Go, res["variant"])), res["nflav"], res["variant"],
+                           None if st is None else -np.abs(st), 1.0)
+        err = abs(res["S"][c] - ref)
+        bound = max(1e-10 * abs(ref), 8 * n * (n + 2) * EPS * sa)
+        print("  config %d n=%d S=%.6e ref=%.6e rel=%.2e kappa=%.1e" % (c, n, res["S"][c], ref,
+              err / abs(ref), sa / abs(ref)), flush=True)
+        assert err <= bound, (c, n, res["S"][c], ref)
+        worst = max(worst, err / abs(ref))
+    return worst
+
+
+def _sample(d, k, seed, maxn=12):
+    rng = np.random.default_rng(seed)
+    ok = np.nonzero(d.n <= maxn)[0]
+    return sorted(rng.choice(ok, size=min(k, ok.size), replace=False).tolist())
+
+
+def test_plain_single(oracle_mod):
+    announce("workload plain_single")
+    d = draw("plain_single")
+    res = gpu_workload(d)
+    _check_sample(oracle_mod, d, res, [0])
+
+
+def test_plain_batch(oracle_mod):
+    announce("workload plain_batch (4096 x n=8, SU(4))")
+    d = draw("plain_batch")
+    res = gpu_workload(d)
+    assert np.all(np.isfinite(res["S"]))
+    _check_sample(oracle_mod, d, res, _sample(d, 24, 2))
+
+
+def test_sym_broken(oracle_mod):
+    announce("workload sym_broken (1024 x n=10, SU(3) flavour mu)")
+    d = draw("sym_broken")
+    res = gpu_workload(d)
+    assert np.all(np.isfinite(res["S"]))
+    _check_sample(oracle_mod, d, res, _sample(d, 4, 3))
+
+
+def test_uneven_prefix(oracle_mod):
+    """First 512 configurations of the uneven SU(6) shift workload (orders 6..12,
+    one persistent launch per order); oracle on sampled orders <= 10."""
+    announce("workload uneven prefix 512")
+    d = draw("uneven", nconf=512)
+    res = gpu_workload(d)
+    assert np.all(np.isfinite(res["S"]))
+    idx = _sample(d, 8, 4, maxn=9) + _sample(d, 1, 5, maxn=10)
+    _check_sample(oracle_mod, d, res, idx)
+
+
+def test_adjoint_workload_forward(oracle_mod):
+    announce("workload adjoint forward (2048 x n=10, SU(4))")
+    d = draw("adjoint")
+    res = gpu_workload(d)
+    assert np.all(np.isfinite(res["S"]))
+    _check_sample(oracle_mod, d, res, _sample(d, 8, 5))
