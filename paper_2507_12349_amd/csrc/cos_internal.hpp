@@ -28,11 +28,16 @@ namespace libcos {
 //   when no vertex below h is half visited (the cycle is still at its head).
 // ---------------------------------------------------------------------------
 
+// Per-level mask records (one 64-byte record per mask, level by level): what a
+// wavefront needs to process a mask, fetched with one scalar load.
+//   [0] mask code (base 3)     [1] ones | (twos << 16)
+//   [2] level-relative row of (m, 0)
+//   [3 + w] level-relative row of (m + e_w, 0) for each vertex w with m_w < 2
+//           (-1 otherwise)
+constexpr int kRecInts = 16;
+
 struct DevPlan {
-    const int32_t *rowbase;   // [3^n] level-relative index of row (m, 0); -1 if m_0 = 0
-    const uint32_t *minfo;    // [3^n] ones | (twos << 16): vertices with m_k = 1, m_k = 2
-    const int2 *rows;         // [total_rows] .x = code << 4 | u, .y = mask index in its level
-    const int32_t *masks;     // [total_masks] mask codes, level by level
+    const int32_t *mrec;      // [total_masks][kRecInts]
     const int4 *levels;       // [2n + 2] .x = first row, .y = #rows, .z = first mask, .w = #masks
     int32_t n;
     int32_t max_rows;         // largest #rows of a level
@@ -61,51 +66,44 @@ __host__ __device__ inline uint32_t current_set(int u, uint32_t ones, uint32_t t
     return c;
 }
 
-struct FwdArgs {
-    DevPlan plan;             // one order per launch
-    const int32_t *order;     // configurations of this order
-    const double *G;
-    const int64_t *Goff;      // may be null: back-to-back layout (uniform n only)
-    const double *stub;
-    double *out;
-    double *ws;               // workspace, ws_per_wg doubles per workgroup
-    int32_t *counter;         // work queue head
-    int64_t ws_per_wg;
+// packing between the caller's layout and the per-lane layout of one order
+struct PackArgs {
+    const double *G;          // caller matrices
+    const int64_t *Goff;      // may be null: back-to-back layout
+    const double *stub;       // caller shift weights or null
+    const int32_t *order;     // configurations of this order, in lane order
+    double *GT;               // [ngroups][nfs][n][n][64]
+    double *sigT;             // [ngroups][nfs][64] or null
+    int32_t *lane_cfg;        // [ngroups][64], -1 = padding lane
+    int32_t n, nfs, nmat, nstub, variant, ngroups, count;
+};
+
+// one level launch (forward or reverse)
+struct LvlArgs {
+    DevPlan plan;
+    const double *GT, *sigT;
+    const int32_t *lane_cfg;
+    const double *cur;        // forward: states of `level`; reverse: adjoints of level + 1
+    double *nxt;              // forward: states of level + 1; reverse: adjoints of `level`
+    int64_t cur_gstride, nxt_gstride;   // doubles per group
+    int32_t cur_row0, nxt_row0;         // first row of the level inside its buffer
+    const double *F;          // reverse: forward states of all levels
+    int64_t F_gstride;
+    int32_t F_row0;
+    int32_t level, group0, nfs, stubs, mpb;
     double W;                 // factor of one closed cycle: w * nflav (uniform) or w
-    int32_t nconf, nfs, nmat, nstub, variant, stubs;
+    double *out;              // forward, last level: S per configuration (may be null)
+    const double *out_bar;    // reverse: dL/dS per configuration
+    double *Gbar_T, *sbar_T;  // reverse: packed gradient accumulators
 };
 
-struct AdjArgs {
-    DevPlan plan;             // one order per launch
-    const int32_t *order;     // configurations of this order
-    const double *G;
-    const int64_t *Goff;
-    const double *stub;
-    const double *out_bar;
-    double *out;              // may be null
-    double *G_bar;
-    double *stub_bar;         // may be null
-    double *ws;
-    int32_t *counter;
-    int64_t ws_per_wg;
-    double W;
-    int32_t nconf, nfs, nmat, nstub, variant, stubs;
-};
-
-// workspace sizes (doubles) per workgroup
-inline int64_t fwd_ws_doubles(const DevPlan &p, int nfs) {
-    int64_t rs = (int64_t)nfs * p.n;
-    return 2 * (int64_t)p.max_rows * rs + (int64_t)p.max_rows * nfs + 8;
-}
-inline int64_t adj_ws_doubles(const DevPlan &p, int nfs) {
-    int64_t rs = (int64_t)nfs * p.n;
-    return p.total_rows * rs + 2 * (int64_t)p.max_rows * rs + (int64_t)p.max_rows * nfs +
-           (int64_t)p.max_masks + 8;
-}
-
+// launchers (cos_level.hip)
+hipError_t launch_pack(const PackArgs &a, hipStream_t s);
+hipError_t launch_unpack(const PackArgs &a, const double *GbT, const double *sbT, double *Gb, double *sb,
+                         hipStream_t s);
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, hipStream_t s);
 // launchers (cos_kernels.hip)
-hipError_t launch_forward(const FwdArgs &a, int grid, int block, hipStream_t s);
-hipError_t launch_adjoint(const AdjArgs &a, int grid, int block, hipStream_t s);
 hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int32_t *sites,
                      const double *tau, int L, double t, double beta, int nmat, const double *mu,
                      const double *alpha, const int64_t *Goff, double *G, double *dG, hipStream_t s);

@@ -1,0 +1,507 @@
+// Level-synchronous kernels: one configuration per lane, 64 configurations
+// per wavefront.
+//
+// The state tables (which rows, heads and currents exist at each level) are
+// the same for every configuration of an order n, so a wavefront walks them
+// with wave-uniform control flow: mask codes, row bases and current sets sit
+// in SGPRs, and every DP state access reads or writes 64 consecutive doubles
+// (one per lane), a single 512-byte transaction.  Each lane holds its own
+// configuration's propagator matrix in VGPRs.  One launch per level (the
+// level = number of visited points, the layer of Alg. 1-3); the launches of
+// a batch run back to back on one stream (and can be captured in a graph).
+//
+// Packed layouts (lane fastest):
+//   GT   [group][flavour][v][w][64]      propagators
+//   sigT [group][flavour][64]            shift weights
+//   state buffers [group][row][flavour][v][64]
+//
+// Forward rules per row (m, u) and flavour l (Results; Alg. 2/3):
+//   acc = f . G_l;  extension to w (m_w < 2): child (m + e_w, u)[w] = c_w acc[w]
+//   (c_w = 2 on a first visit); shift head on the partner of a vertex just
+//   reached for the first time: + (-sigma_l) f[w] (doubled on the start row);
+//   close: t_m = W sum_{u,l} acc[u]; the next cycle opens at
+//   h = min{k : m_k = 1} with value t_m in every flavour, or S = t_m at the
+//   full mask.
+#include "cos_internal.hpp"
+
+namespace libcos {
+
+#define COS_RF(x) __builtin_amdgcn_readfirstlane(x)
+
+typedef __attribute__((address_space(3))) double lds_double;
+// read-only tables read at wave-uniform addresses: through the constant
+// address space they are fetched with scalar loads
+typedef const __attribute__((address_space(4))) int32_t cint32;
+
+// one mask of a level: its code bits, row base and child row bases
+template <int N>
+struct MaskRec {
+    int code, rb;
+    uint32_t ones, twos;
+    int crb[N];   // level-relative row of (m + e_w, 0); valid where m_w < 2
+};
+
+template <int N>
+__device__ __forceinline__ MaskRec<N> load_rec(const DevPlan &P, int gi) {
+    const cint32 *r = (const cint32 *)(P.mrec + (int64_t)gi * kRecInts);
+    MaskRec<N> m;
+    m.code = r[0];
+    const uint32_t info = (uint32_t)r[1];
+    m.ones = info & 0xffffu;
+    m.twos = info >> 16;
+    m.rb = r[2];
+#pragma unroll
+    for (int w = 0; w < N; ++w) m.crb[w] = r[3 + w];
+    return m;
+}
+
+__device__ __forceinline__ int4 load_level(const DevPlan &P, int l) {
+    const cint32 *p = (const cint32 *)(P.levels + l);
+    return make_int4(p[0], p[1], p[2], p[3]);
+}
+
+// child row base for the vertex h that opens the next cycle (h is wave-uniform;
+// a select chain keeps the record in scalar registers)
+template <int N>
+__device__ __forceinline__ int close_row_base(const MaskRec<N> &M, int h) {
+    int rb = 0;
+#pragma unroll
+    for (int w = 0; w < N; ++w) rb = (w == h) ? M.crb[w] : rb;
+    return rb;
+}
+
+// LDS byte address of a __shared__ pointer
+__device__ __forceinline__ uint32_t lds_addr(double *p) {
+    return (uint32_t)(uintptr_t)(lds_double *)p;
+}
+
+// ---------------------------------------------------------------------------
+// packing: caller layout -> per-lane layout (zeros in padding lanes)
+// ---------------------------------------------------------------------------
+__global__ void pack_kernel(const PackArgs A) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = A.n, nfs = A.nfs;
+    const int64_t per_group = (int64_t)nfs * N * N * 64;
+    if (i >= per_group * A.ngroups) return;
+    const int lane = (int)(i & 63);
+    int64_t rest = i >> 6;
+    const int w = (int)(rest % N); rest /= N;
+    const int v = (int)(rest % N); rest /= N;
+    const int l = (int)(rest % nfs); rest /= nfs;
+    const int g = (int)rest;
+    const int slot = g * 64 + lane;
+    const int c = slot < A.count ? A.order[slot] : -1;
+    double x = 0.0;
+    if (c >= 0) {
+        const int64_t off = A.Goff ? A.Goff[c] : (int64_t)c * A.nmat * N * N;
+        x = A.G[off + ((int64_t)(A.variant ? l : 0) * N + v) * N + w];
+    }
+    A.GT[i] = x;
+    if (v == 0 && w == 0) {
+        const int64_t si = ((int64_t)g * nfs + l) * 64 + lane;
+        if (A.sigT) A.sigT[si] = (c >= 0 && A.stub) ? A.stub[(int64_t)c * A.nstub + (A.variant ? l : 0)] : 0.0;
+        if (l == 0) A.lane_cfg[slot] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// forward: level -> level + 1
+//
+// A workgroup of WPB wavefronts serves one group of 64 configurations and
+// WPB consecutive blocks of `mpb` masks.  G_l of the 64 lanes sits in LDS
+// ([v][w][lane], conflict-free: the lanes read consecutive words), loaded
+// once per flavour by the whole workgroup.  With one flavour the close sums
+// stay in registers; with several, the flavour loop is outermost and the
+// per-mask sums wait in LDS until every flavour is done.
+// ---------------------------------------------------------------------------
+template <int N>
+__device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
+                                        double *__restrict__ nxt, int nfs, int lam, int u, int r, bool start,
+                                        double sgx, double &cp, double &dext) {
+    const uint32_t ones = M.ones, twos = M.twos;
+    const uint32_t cm = current_set(u, ones, twos);
+    const double *__restrict__ src = cur + ((int64_t)r * nfs + lam) * N * 64;
+    // G comes from LDS for every row: an opaque base keeps the N^2 reads inside
+    // the row instead of hoisted into N^2 registers for the whole loop
+    asm volatile("" : "+v"(gaddr));
+    const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
+    double f[N], acc[N];
+#pragma unroll
+    for (int v = 0; v < N; ++v) f[v] = ((cm >> v) & 1u) ? src[v * 64] : 0.0;
+    if (start) {
+#pragma unroll
+        for (int v = 0; v < N; ++v) f[v] = v == 0 ? 1.0 : 0.0;   // start: (e_0, 0, 0) = 1
+    }
+#pragma unroll
+    for (int w = 0; w < N; ++w) acc[w] = 0.0;
+#pragma unroll
+    for (int v = 0; v < N; ++v)
+#pragma unroll
+        for (int w = 0; w < N; ++w) acc[w] = __builtin_fma(f[v], Gs[(v * N + w) * 64], acc[w]);
+#pragma unroll
+    for (int w = 0; w < N; ++w)
+        if (w == u) cp += acc[w];
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+        const uint32_t bit = 1u << w;
+        if (twos & bit) continue;
+        const bool first = !(ones & bit);
+        double val = first ? 2.0 * acc[w] : acc[w];
+        if (!first && (cm & bit)) val = __builtin_fma(-sgx, f[w], val);
+        if (w == 0 && u == 0 && !(twos & 1u)) {
+            dext = val;   // m_0 = 1: the next cycle opens on this same slot
+            continue;
+        }
+        const uint32_t ctw = first ? twos : (twos | bit);
+        const int crow = M.crb[w] + head_slot(u, ctw);
+        nxt[((int64_t)crow * nfs + lam) * N * 64 + w * 64] = val;
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void fwd_close(const MaskRec<N> &M, double *__restrict__ nxt, int nfs, int lam, double t,
+                                          double dext) {
+    const int h = __builtin_ctz(M.ones);
+    const int crow = close_row_base<N>(M, h) + head_slot(h, M.twos | (1u << h));
+    nxt[((int64_t)crow * nfs + lam) * N * 64 + h * 64] = t + (h == 0 ? dext : 0.0);
+}
+
+template <int N, bool MULTI>
+__global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
+    extern __shared__ double lds[];
+    double *Gs_all = lds;                      // [N * N][64]
+    double *cs = lds + N * N * 64;             // MULTI: [wpb][mpb][nfs + 1][64]
+    const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
+    const int wpb = blockDim.x >> 6;
+    const DevPlan &P = A.plan;
+    const int4 L = load_level(P, A.level);
+    const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
+    const int mb1 = min(mb0 + A.mpb, L.w);     // may be empty: the wave still joins the barriers
+    const int gl = blockIdx.y, g = A.group0 + gl;
+    const int nfs = A.nfs;
+    const int64_t RS = (int64_t)nfs * N * 64;
+    const double *__restrict__ cur = A.cur + gl * A.cur_gstride + (int64_t)A.cur_row0 * RS + lane;
+    double *__restrict__ nxt = A.nxt + gl * A.nxt_gstride + (int64_t)A.nxt_row0 * RS + lane;
+    const uint32_t gaddr = lds_addr(Gs_all) + lane * 8u;
+    const int cfg = A.lane_cfg[g * 64 + lane];
+    const bool last = A.level == 2 * N, start = A.level == 1;
+    double *csw = cs + (size_t)wave * A.mpb * (nfs + 1) * 64 + lane;
+    if (MULTI)
+        for (int i = 0; i < (mb1 - mb0) * (nfs + 1); ++i) csw[i * 64] = 0.0;
+
+    for (int lam = 0; lam < nfs; ++lam) {
+        __syncthreads();
+        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * N * N * 64;
+        for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) Gs_all[i] = gsrc[i];
+        __syncthreads();
+        const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
+        for (int mi = mb0; mi < mb1; ++mi) {
+            const MaskRec<N> M = load_rec<N>(P, L.z + mi);
+            const uint32_t ones = M.ones, twos = M.twos;
+            const double sgx = sg * (M.code == 1 ? 2.0 : 1.0);
+            uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
+            int u = 0, slot = 0;
+            double cp = 0.0, dext = 0.0;
+            while (true) {
+                fwd_row<N>(M, gaddr, cur, nxt, nfs, lam, u, M.rb + slot, start, sgx, cp, dext);
+                if (!hs) break;
+                u = __builtin_ctz(hs);
+                hs &= hs - 1u;
+                ++slot;
+            }
+            if (MULTI) {
+                double *c = csw + (size_t)(mi - mb0) * (nfs + 1) * 64;
+                c[0] += cp;
+                c[(1 + lam) * 64] = dext;
+            } else {
+                const double t = A.W * cp;
+                if (last) {
+                    if (cfg >= 0 && A.out) A.out[cfg] = t;
+                } else if (ones) {
+                    fwd_close<N>(M, nxt, nfs, 0, t, dext);
+                }
+            }
+        }
+    }
+    if (MULTI) {
+        for (int mi = mb0; mi < mb1; ++mi) {
+            const MaskRec<N> M = load_rec<N>(P, L.z + mi);
+            const double *c = csw + (size_t)(mi - mb0) * (nfs + 1) * 64;
+            const double t = A.W * c[0];
+            if (last) {
+                if (cfg >= 0 && A.out) A.out[cfg] = t;
+            } else if (M.ones) {
+                for (int lam = 0; lam < nfs; ++lam) fwd_close<N>(M, nxt, nfs, lam, t, c[(1 + lam) * 64]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse: B = dS/dF at level `level` from B at level + 1; dS/dG and
+// dS/dsigma accumulate per lane in registers and are added to the packed
+// accumulators at the end of the block.
+//   a[w] = c_w B(m + e_w, u)[w] (open w) + [w == u] W tbar_m,
+//   tbar_m = sum_l B(m + e_h, h, l)[h] (1 at the full mask, 0 when dropped),
+//   B(m, u)[v] = sum_w G[v][w] a[w] + [m_v = 1, v current] (-sigma) a[v],
+//   Gbar[v][w] += f[v] a[w],  sigmabar += -f[w] B(m + e_w, u)[w] (shift edges).
+// ---------------------------------------------------------------------------
+// one half of a row's reverse step: vertices v in [VLO, VHI) of B and of the
+// dS/dG rows; the other half runs on the partner wavefront
+template <int N, int VLO, int VHI>
+__device__ __forceinline__ void adj_block(const LvlArgs &A, const DevPlan &P, const int4 &L, int mb0, int mb1, int g,
+                                          const double *__restrict__ F, const double *__restrict__ Bn,
+                                          double *__restrict__ Bc, const double *tbw, uint32_t gaddr0, int lam) {
+    constexpr int NV = VHI - VLO;
+    const int nfs = A.nfs;
+    const int lane = threadIdx.x & 63;
+    double gacc[NV > 0 ? NV : 1][N];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int w = 0; w < N; ++w) gacc[v][w] = 0.0;
+    const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
+    double sacc = 0.0;
+    for (int mi = mb0; mi < mb1; ++mi) {
+        const MaskRec<N> M = load_rec<N>(P, L.z + mi);
+        const uint32_t ones = M.ones, twos = M.twos;
+        const int rb = M.rb;
+        const double sc = (M.code == 1 ? 2.0 : 1.0);
+        const double tb = tbw[(mi - mb0) * 64];
+        uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;
+        int u = 0, slot = 0;
+        while (true) {
+            const int r = rb + slot;
+            const uint32_t cm = current_set(u, ones, twos);
+            double f[NV > 0 ? NV : 1], a[N];
+            const double *__restrict__ src = F + ((int64_t)r * nfs + lam) * N * 64;
+#pragma unroll
+            for (int v = VLO; v < VHI; ++v) f[v - VLO] = ((cm >> v) & 1u) ? src[v * 64] : 0.0;
+            if (A.level == 1) {
+#pragma unroll
+                for (int v = VLO; v < VHI; ++v) f[v - VLO] = v == 0 ? 1.0 : 0.0;
+            }
+#pragma unroll
+            for (int w = 0; w < N; ++w) {
+                const uint32_t bit = 1u << w;
+                a[w] = 0.0;
+                if (twos & bit) continue;
+                const bool first = !(ones & bit);
+                const uint32_t ctw = first ? twos : (twos | bit);
+                const int crow = M.crb[w] + head_slot(u, ctw);
+                const double bc = Bn[((int64_t)crow * nfs + lam) * N * 64 + w * 64];
+                a[w] = first ? 2.0 * bc : bc;
+                if (w >= VLO && w < VHI && !first && (cm & bit)) sacc = __builtin_fma(-sc * f[w - VLO], bc, sacc);
+            }
+            // the close of this row feeds t_m: dS/dacc[u] gains W tbar
+#pragma unroll
+            for (int w = 0; w < N; ++w)
+                if (w == u) a[w] += tb;
+            uint32_t gaddr = gaddr0;
+            asm volatile("" : "+v"(gaddr));
+            const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
+            double *__restrict__ dst = Bc + ((int64_t)r * nfs + lam) * N * 64;
+#pragma unroll
+            for (int v = VLO; v < VHI; ++v) {
+                double b = 0.0;
+#pragma unroll
+                for (int w = 0; w < N; ++w) b = __builtin_fma(Gs[(v * N + w) * 64], a[w], b);
+                const uint32_t bit = 1u << v;
+                if ((ones & bit) && (cm & bit)) {
+                    // shift edge out of this slot: child adjoint, without the close term
+                    const double bcv = (v == u) ? a[v] - tb : a[v];
+                    b = __builtin_fma(-sg * sc, bcv, b);
+                }
+                if (cm & bit) dst[v * 64] = b;
+            }
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int w = 0; w < N; ++w) gacc[v][w] = __builtin_fma(f[v], a[w], gacc[v][w]);
+            if (!hs) break;
+            u = __builtin_ctz(hs);
+            hs &= hs - 1u;
+            ++slot;
+        }
+    }
+    if (mb0 < mb1) {
+        double *__restrict__ gb = A.Gbar_T + ((int64_t)(g * nfs + lam) * N * N) * 64 + lane;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int w = 0; w < N; ++w) atomicAdd(gb + ((v + VLO) * N + w) * 64, gacc[v][w]);
+        if (A.stubs) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
+    }
+}
+
+// slice k of SL equal parts of [0, N)
+template <int N, int SL, int K>
+struct Slice {
+    static constexpr int lo = K * N / SL, hi = (K + 1) * N / SL;
+};
+
+template <int N, int SL, int K>
+__device__ __forceinline__ void adj_slice(const LvlArgs &A, const DevPlan &P, const int4 &L, int mb0, int mb1, int g,
+                                          const double *__restrict__ F, const double *__restrict__ Bn,
+                                          double *__restrict__ Bc, const double *tbw, uint32_t gaddr0, int lam,
+                                          int k) {
+    if constexpr (K < SL) {
+        if (k == K)
+            adj_block<N, Slice<N, SL, K>::lo, Slice<N, SL, K>::hi>(A, P, L, mb0, mb1, g, F, Bn, Bc, tbw, gaddr0, lam);
+        else
+            adj_slice<N, SL, K + 1>(A, P, L, mb0, mb1, g, F, Bn, Bc, tbw, gaddr0, lam, k);
+    }
+}
+
+// reverse level kernel: SL wavefronts share a block of masks, one per slice
+// of the vertex range (fewer dS/dG accumulators per lane, more waves per SIMD)
+template <int N, int SL>
+__global__ void __launch_bounds__(512) level_adj_kernel(const LvlArgs A) {
+    extern __shared__ double lds[];
+    double *Gs_all = lds;                     // [N * N][64]
+    double *tbs = lds + N * N * 64;           // [wpb / SL][mpb][64]: W * tbar per mask
+    const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
+    const int team = wave / SL, slice = wave % SL;
+    const int nteams = (blockDim.x >> 6) / SL;
+    const DevPlan &P = A.plan;
+    const int4 L = load_level(P, A.level);
+    const int mb0 = (blockIdx.x * nteams + team) * A.mpb;
+    const int mb1 = min(mb0 + A.mpb, L.w);    // may be empty: the wave still joins the barriers
+    const int gl = blockIdx.y, g = A.group0 + gl;
+    const int nfs = A.nfs;
+    const int64_t RS = (int64_t)nfs * N * 64;
+    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * RS + lane;
+    const double *__restrict__ Bn = A.cur + gl * A.cur_gstride + lane;   // level + 1
+    double *__restrict__ Bc = A.nxt + gl * A.nxt_gstride + lane;         // level
+    const int cfg = A.lane_cfg[g * 64 + lane];
+    const double obar = cfg >= 0 ? A.out_bar[cfg] : 0.0;
+    const uint32_t gaddr0 = lds_addr(Gs_all) + lane * 8u;
+    double *tbw = tbs + (size_t)team * A.mpb * 64 + lane;
+
+    if (slice == 0) {
+        for (int mi = mb0; mi < mb1; ++mi) {
+            const MaskRec<N> M = load_rec<N>(P, L.z + mi);
+            const uint32_t ones = M.ones, twos = M.twos;
+            double tb = 0.0;
+            if (A.level == 2 * N) {
+                tb = obar;
+            } else if (ones) {
+                const int h = __builtin_ctz(ones);
+                const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
+                for (int kk = 0; kk < nfs; ++kk) tb += Bn[((int64_t)crow * nfs + kk) * N * 64 + h * 64];
+            }
+            tbw[(mi - mb0) * 64] = A.W * tb;
+        }
+    }
+    for (int lam = 0; lam < nfs; ++lam) {
+        __syncthreads();   // also publishes tbar of the first wave of each team
+        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * N * N * 64;
+        for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) Gs_all[i] = gsrc[i];
+        __syncthreads();
+        adj_slice<N, SL, 0>(A, P, L, mb0, mb1, g, F, Bn, Bc, tbw, gaddr0, lam, slice);
+    }
+}
+
+__global__ void zero_kernel(double *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// packed gradients -> caller layout
+__global__ void unpack_kernel(const PackArgs A, const double *__restrict__ GbT, const double *__restrict__ sbT,
+                              double *__restrict__ Gb, double *__restrict__ sb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N = A.n, nfs = A.nfs;
+    const int64_t per_group = (int64_t)nfs * N * N * 64;
+    if (i >= per_group * A.ngroups) return;
+    const int lane = (int)(i & 63);
+    int64_t rest = i >> 6;
+    const int w = (int)(rest % N); rest /= N;
+    const int v = (int)(rest % N); rest /= N;
+    const int l = (int)(rest % nfs); rest /= nfs;
+    const int g = (int)rest;
+    const int slot = g * 64 + lane;
+    if (slot >= A.count) return;
+    const int c = A.order[slot];
+    const int64_t off = A.Goff ? A.Goff[c] : (int64_t)c * A.nmat * N * N;
+    Gb[off + ((int64_t)(A.variant ? l : 0) * N + v) * N + w] = GbT[i];
+    if (v == 0 && w == 0 && sb) sb[(int64_t)c * A.nstub + (A.variant ? l : 0)] = sbT[((int64_t)g * nfs + l) * 64 + lane];
+}
+
+hipError_t launch_pack(const PackArgs &a, hipStream_t s) {
+    const int64_t tot = (int64_t)a.ngroups * a.nfs * a.n * a.n * 64;
+    hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(const PackArgs &a, const double *GbT, const double *sbT, double *Gb, double *sb,
+                         hipStream_t s) {
+    const int64_t tot = (int64_t)a.ngroups * a.nfs * a.n * a.n * 64;
+    hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, GbT, sbT, Gb, sb);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+int fwd_waves_per_block() { return 8; }
+// wavefronts sharing one row in the reverse sweep (slices of the vertex range)
+int adj_slices(int n) { return n >= 8 ? 4 : 2; }
+
+// raise a kernel's dynamic-LDS limit when a launch needs more than 64 KB
+static hipError_t allow_lds(const void *fn, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, hipStream_t s) {
+    const int n = a.plan.n;
+    const int wpb = fwd_waves_per_block();
+    if (reverse) {
+        const int sl = adj_slices(n);
+        const int nteams = wpb / sl;
+        const size_t shm = (size_t)n * n * 64 * sizeof(double) + (size_t)nteams * a.mpb * 64 * sizeof(double);
+        const dim3 grid((unsigned)((nblocks + nteams - 1) / nteams), (unsigned)ngroups);
+        switch (n) {
+#define COS_ADJ_CASE(K, SLK)                                                              \
+    case K: {                                                                             \
+        hipError_t e = allow_lds((const void *)level_adj_kernel<K, SLK>, shm);            \
+        if (e != hipSuccess) return e;                                                    \
+        hipLaunchKernelGGL((level_adj_kernel<K, SLK>), grid, dim3(64 * wpb), shm, s, a);  \
+        break;                                                                            \
+    }
+            COS_ADJ_CASE(1, 2) COS_ADJ_CASE(2, 2) COS_ADJ_CASE(3, 2) COS_ADJ_CASE(4, 2)
+            COS_ADJ_CASE(5, 2) COS_ADJ_CASE(6, 2) COS_ADJ_CASE(7, 2) COS_ADJ_CASE(8, 4)
+            COS_ADJ_CASE(9, 4) COS_ADJ_CASE(10, 4) COS_ADJ_CASE(11, 4) COS_ADJ_CASE(12, 4)
+#undef COS_ADJ_CASE
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    const bool multi = a.nfs > 1;
+    const size_t shm = (size_t)n * n * 64 * sizeof(double) +
+                       (multi ? (size_t)wpb * a.mpb * (a.nfs + 1) * 64 * sizeof(double) : 0);
+    const dim3 grid((unsigned)((nblocks + wpb - 1) / wpb), (unsigned)ngroups);
+    switch (n) {
+#define COS_FWD_CASE(K)                                                                                    \
+    case K: {                                                                                              \
+        hipError_t e = multi ? allow_lds((const void *)level_fwd_kernel<K, true>, shm)                     \
+                             : allow_lds((const void *)level_fwd_kernel<K, false>, shm);                   \
+        if (e != hipSuccess) return e;                                                                     \
+        if (multi) hipLaunchKernelGGL((level_fwd_kernel<K, true>), grid, dim3(64 * wpb), shm, s, a);       \
+        else hipLaunchKernelGGL((level_fwd_kernel<K, false>), grid, dim3(64 * wpb), shm, s, a);            \
+        break;                                                                                             \
+    }
+        COS_FWD_CASE(1) COS_FWD_CASE(2) COS_FWD_CASE(3) COS_FWD_CASE(4)
+        COS_FWD_CASE(5) COS_FWD_CASE(6) COS_FWD_CASE(7) COS_FWD_CASE(8)
+        COS_FWD_CASE(9) COS_FWD_CASE(10) COS_FWD_CASE(11) COS_FWD_CASE(12)
+#undef COS_FWD_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace libcos

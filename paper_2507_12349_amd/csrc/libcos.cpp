@@ -51,6 +51,7 @@ struct HostPlan {
     std::vector<int2> rows;
     std::vector<int32_t> masks;
     std::vector<int4> levels;       // [2n + 2]
+    std::vector<int32_t> mrec;      // [masks][kRecInts]
     int32_t max_rows = 0, max_masks = 0;
     int64_t states = 0, ext = 0, closes = 0, shift_edges = 0;
 };
@@ -113,6 +114,18 @@ void build_host_plan(int n, HostPlan &P) {
     }
     P.closes = P.states;
     P.levels[2 * n + 1] = make_int4((int)P.rows.size(), 0, (int)P.masks.size(), 0);
+    P.mrec.assign(P.masks.size() * kRecInts, -1);
+    for (size_t i = 0; i < P.masks.size(); ++i) {
+        const int code = P.masks[i];
+        const uint32_t ones = P.minfo[code] & 0xffffu, twos = P.minfo[code] >> 16;
+        int32_t *r = &P.mrec[i * kRecInts];
+        r[0] = code;
+        r[1] = (int32_t)P.minfo[code];
+        r[2] = P.rowbase[code];
+        for (int w = 0; w < n; ++w)
+            if (!((twos >> w) & 1u)) r[3 + w] = P.rowbase[code + pow3(w)];
+        (void)ones;
+    }
 }
 
 struct DevTables {
@@ -149,31 +162,20 @@ cos_status device_plan(int dev, int n, DevPlan *out) {
         return COS_OK;
     }
     auto hp = host_plan(n);
-    const size_t s1 = align_up(hp->rowbase.size() * 4), s2 = align_up(hp->minfo.size() * 4),
-                 s3 = align_up(hp->rows.size() * sizeof(int2)), s4 = align_up(hp->masks.size() * 4),
-                 s5 = align_up(hp->levels.size() * sizeof(int4));
+    const size_t s1 = align_up(hp->mrec.size() * 4), s2 = align_up(hp->levels.size() * sizeof(int4));
     char *mem = nullptr;
-    if (hipMalloc((void **)&mem, s1 + s2 + s3 + s4 + s5) != hipSuccess)
+    if (hipMalloc((void **)&mem, s1 + s2) != hipSuccess)
         return fail(COS_ENOMEM, "device allocation of the state tables for n=%d failed", n);
-    hipError_t e = hipSuccess;
-    size_t o = 0;
-    e = e ? e : hipMemcpy(mem + o, hp->rowbase.data(), hp->rowbase.size() * 4, hipMemcpyHostToDevice); o += s1;
-    e = e ? e : hipMemcpy(mem + o, hp->minfo.data(), hp->minfo.size() * 4, hipMemcpyHostToDevice); o += s2;
-    e = e ? e : hipMemcpy(mem + o, hp->rows.data(), hp->rows.size() * sizeof(int2), hipMemcpyHostToDevice); o += s3;
-    e = e ? e : hipMemcpy(mem + o, hp->masks.data(), hp->masks.size() * 4, hipMemcpyHostToDevice); o += s4;
-    e = e ? e : hipMemcpy(mem + o, hp->levels.data(), hp->levels.size() * sizeof(int4), hipMemcpyHostToDevice);
+    hipError_t e = hipMemcpy(mem, hp->mrec.data(), hp->mrec.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(mem + s1, hp->levels.data(), hp->levels.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(mem);
         return fail(COS_EDEVICE, "upload of the state tables failed: %s", hipGetErrorString(e));
     }
     DevTables t;
     t.mem = mem;
-    o = 0;
-    t.dp.rowbase = (const int32_t *)(mem + o); o += s1;
-    t.dp.minfo = (const uint32_t *)(mem + o); o += s2;
-    t.dp.rows = (const int2 *)(mem + o); o += s3;
-    t.dp.masks = (const int32_t *)(mem + o); o += s4;
-    t.dp.levels = (const int4 *)(mem + o);
+    t.dp.mrec = (const int32_t *)mem;
+    t.dp.levels = (const int4 *)(mem + s1);
     t.dp.n = n;
     t.dp.max_rows = hp->max_rows;
     t.dp.max_masks = hp->max_masks;
@@ -204,35 +206,32 @@ cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
     return COS_OK;
 }
 
-// waves per workgroup: a multiple of the flavour-slot count (each wave works
-// on one flavour, so G_l stays uniform over the wave)
-int pick_waves(int nfs, int max_waves) {
-    int w = nfs * std::max(1, max_waves / nfs);
-    return std::min(w, std::max(nfs, 1) * std::max(1, 16 / std::max(nfs, 1)));
-}
-
 }  // namespace
+
+// all configurations of one order inside a batch
+struct OrderGroup {
+    int n = 0, first = 0, count = 0;   // configurations d_order[first .. first + count)
+    int ngroups = 0;                   // 64 configurations per group (one per lane)
+    int64_t gt_off = 0, sig_off = 0, lane_off = 0;   // offsets into the packed buffers
+    int chunk_fwd = 1, chunk_adj = 1;  // groups per chunk (bounded workspace)
+    std::shared_ptr<HostPlan> hp;
+};
 
 struct cos_batch_s {
     int dev = 0, ncu = 0;
     int32_t nconf = 0, nflav = 0, variant = 0, flags = 0;
     int nfs = 1, nmat = 1, nstub = 1;
     bool uniform_n = true;
-    int nmax = 0;
-    std::vector<int32_t> n_host;
     DevPlan plans[COS_NMAX + 1]{};
-    int32_t *d_order = nullptr;   // forward schedule (most work first)
-    int32_t *d_counter = nullptr;
-    double *d_ws = nullptr;
-    std::vector<int64_t> fwd_ws;   // per group: doubles per workgroup
-    std::vector<int> fwd_grid;     // per group: workgroups
-    int grid = 0, block = 256;
-    std::vector<std::pair<int, std::pair<int, int>>> groups;   // order -> [start, count) in d_order
-
-    double *d_adj_ws = nullptr;
-    std::vector<int64_t> adj_ws;
-    std::vector<int> adj_grid;
-    int adj_block = 256;
+    std::vector<OrderGroup> orders;    // largest order first
+    int32_t *d_order = nullptr;        // configurations grouped by order
+    double *d_GT = nullptr, *d_sigT = nullptr;
+    int32_t *d_lane = nullptr;
+    double *d_win = nullptr;           // forward level windows
+    int64_t win_doubles = 0;
+    // reverse sweep (allocated on first use)
+    double *d_Fall = nullptr, *d_GbT = nullptr, *d_sbT = nullptr;
+    int64_t fall_doubles = 0;
 };
 
 extern "C" {
@@ -293,46 +292,51 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
     b->nfs = variant == COS_FLAVOUR ? nflav : 1;
     b->nmat = b->nfs;
     b->nstub = b->nfs;
-    b->n_host.assign(n, n + nconf);
     bool seen[COS_NMAX + 1] = {false};
     for (int c = 0; c < nconf; ++c) seen[n[c]] = true;
     for (int k = 1; k <= COS_NMAX; ++k)
         if (seen[k]) {
             if ((st = device_plan(dev, k, &b->plans[k]))) return st;
-            b->nmax = k;
         }
     b->uniform_n = std::all_of(n, n + nconf, [&](int32_t x) { return x == n[0]; });
 
-    // schedule: configurations grouped by order, largest order first; each
-    // group is one persistent launch whose workgroups pull from a queue
+    // configurations grouped by order, largest order first; 64 per group
     std::vector<int32_t> order(nconf);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return n[a] > n[c]; });
+    int64_t gt = 0, sg = 0, ln = 0, win = 0;
     for (int i = 0; i < nconf;) {
         int j = i;
         while (j < nconf && n[order[j]] == n[order[i]]) ++j;
-        b->groups.push_back({n[order[i]], {i, j - i}});
+        OrderGroup o;
+        o.n = n[order[i]];
+        o.first = i;
+        o.count = j - i;
+        o.ngroups = (o.count + 63) / 64;
+        o.gt_off = gt;
+        o.sig_off = sg;
+        o.lane_off = ln;
+        {
+            std::lock_guard<std::mutex> lk(g_mu);
+            o.hp = host_plan(o.n);
+        }
+        const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        const int64_t per_group = 2 * (int64_t)o.hp->max_rows * rs;
+        o.chunk_fwd = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
+        win = std::max(win, per_group * o.chunk_fwd);
+        gt += (int64_t)o.ngroups * b->nfs * o.n * o.n * 64;
+        sg += (int64_t)o.ngroups * b->nfs * 64;
+        ln += (int64_t)o.ngroups * 64;
+        b->orders.push_back(o);
         i = j;
     }
-    const int waves = pick_waves(b->nfs, 4);
-    b->block = 64 * waves;
-    const int per_cu = std::max(1, 16 / waves);
-    b->grid = std::max(1, std::min<int>(nconf, ncu * per_cu));
-    // groups run one after another and share the workspace; each group gets
-    // as many workgroups as it can use, capped so the workspace stays bounded
-    int64_t total = 0;
-    for (auto &g : b->groups) {
-        const int64_t ws = (fwd_ws_doubles(b->plans[g.first], b->nfs) + 31) & ~(int64_t)31;
-        const int64_t cap = std::max<int64_t>(1, kWorkspaceCap / (8 * ws));
-        const int gg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)b->grid, (int64_t)g.second.second, cap}));
-        b->fwd_ws.push_back(ws);
-        b->fwd_grid.push_back(gg);
-        total = std::max(total, ws * gg);
-    }
+    b->win_doubles = win;
     if (hipMalloc((void **)&b->d_order, sizeof(int32_t) * nconf) != hipSuccess ||
-        hipMalloc((void **)&b->d_counter, 256) != hipSuccess ||
-        hipMalloc((void **)&b->d_ws, sizeof(double) * (size_t)total) != hipSuccess)
-        return fail(COS_ENOMEM, "workspace allocation failed (%.1f MB)", 8.0 * total / 1e6);
+        hipMalloc((void **)&b->d_GT, sizeof(double) * gt) != hipSuccess ||
+        hipMalloc((void **)&b->d_sigT, sizeof(double) * sg) != hipSuccess ||
+        hipMalloc((void **)&b->d_lane, sizeof(int32_t) * ln) != hipSuccess ||
+        hipMalloc((void **)&b->d_win, sizeof(double) * win) != hipSuccess)
+        return fail(COS_ENOMEM, "workspace allocation failed (%.1f MB)", 8.0 * (gt + sg + win) / 1e6);
     HIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nconf, hipMemcpyHostToDevice));
     *out = b.release();
     return COS_OK;
@@ -341,9 +345,13 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
 cos_status cos_batch_destroy(cos_batch_t b) {
     if (!b) return COS_OK;
     (void)hipFree(b->d_order);
-    (void)hipFree(b->d_counter);
-    (void)hipFree(b->d_ws);
-    (void)hipFree(b->d_adj_ws);
+    (void)hipFree(b->d_GT);
+    (void)hipFree(b->d_sigT);
+    (void)hipFree(b->d_lane);
+    (void)hipFree(b->d_win);
+    (void)hipFree(b->d_Fall);
+    (void)hipFree(b->d_GbT);
+    (void)hipFree(b->d_sbT);
     delete b;
     return COS_OK;
 }
@@ -357,57 +365,104 @@ static cos_status check_batch_ptrs(cos_batch_t b, const double *d_G, const int64
     return COS_OK;
 }
 
+static PackArgs pack_args(cos_batch_t b, const OrderGroup &o, const double *d_G, const int64_t *d_Goff,
+                          const double *d_stub) {
+    PackArgs p;
+    std::memset(&p, 0, sizeof(p));
+    p.G = d_G;
+    p.Goff = d_Goff;
+    p.stub = (b->flags & COS_F_STUBS) ? d_stub : nullptr;
+    p.order = b->d_order + o.first;
+    p.GT = b->d_GT + o.gt_off;
+    p.sigT = b->d_sigT + o.sig_off;
+    p.lane_cfg = b->d_lane + o.lane_off;
+    p.n = o.n;
+    p.nfs = b->nfs;
+    p.nmat = b->nmat;
+    p.nstub = b->nstub;
+    p.variant = b->variant;
+    p.ngroups = o.ngroups;
+    p.count = o.count;
+    return p;
+}
+
+static LvlArgs level_args(cos_batch_t b, const OrderGroup &o, double cycle_weight) {
+    LvlArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.plan = b->plans[o.n];
+    a.GT = b->d_GT + o.gt_off;
+    a.sigT = b->d_sigT + o.sig_off;
+    a.lane_cfg = b->d_lane + o.lane_off;
+    a.nfs = b->nfs;
+    a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
+    a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
+    return a;
+}
+
+// masks per wavefront for a level of `nm` masks and `ng` groups: up to `cap1`
+// (to amortise loading G into LDS and flushing accumulators), fewer when the
+// level is small so that its rows spread over enough wavefronts
+static int masks_per_block(int nfs, int nm, int ng, int ncu, int cap1 = 8) {
+    const int cap = nfs <= 1 ? cap1 : std::max(2, 16 / (nfs + 1));
+    const int64_t want_waves = (int64_t)ncu * 16;
+    const int64_t per = ((int64_t)nm * ng) / std::max<int64_t>(1, want_waves);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(cap, per));
+}
+
 cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
                                      const double *d_stub, double cycle_weight, double *d_out,
                                      void *stream) {
     cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
     if (st) return st;
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
-    // one persistent launch per distinct order (a uniform batch is one launch)
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        const auto &g = b->groups[gi];
-        FwdArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.plan = b->plans[g.first];
-        a.order = b->d_order + g.second.first;
-        a.G = d_G;
-        a.Goff = d_Goff;
-        a.stub = (b->flags & COS_F_STUBS) ? d_stub : nullptr;
-        a.out = d_out;
-        a.ws = b->d_ws;
-        a.counter = b->d_counter;
-        a.ws_per_wg = b->fwd_ws[gi];
-        a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
-        a.nconf = g.second.second;
-        a.nfs = b->nfs;
-        a.nmat = b->nmat;
-        a.nstub = b->nstub;
-        a.variant = b->variant;
-        a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
-        HIP_TRY(launch_forward(a, b->fwd_grid[gi], b->block, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    for (const OrderGroup &o : b->orders) {
+        HIP_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
+        const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        const int64_t gstride = (int64_t)o.hp->max_rows * rs;
+        for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_fwd) {
+            const int cg = std::min(o.chunk_fwd, o.ngroups - c0);
+            double *win0 = b->d_win, *win1 = b->d_win + gstride * cg;
+            for (int l = 1; l <= 2 * o.n; ++l) {
+                LvlArgs a = level_args(b, o, cycle_weight);
+                a.level = l;
+                a.group0 = c0;
+                a.cur = (l & 1) ? win1 : win0;
+                a.nxt = (l & 1) ? win0 : win1;
+                a.cur_gstride = a.nxt_gstride = gstride;
+                const int nm = o.hp->levels[l].w;
+                a.mpb = masks_per_block(b->nfs, nm, cg, b->ncu);
+                a.out = d_out;
+                HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, s));
+            }
+        }
     }
     return COS_OK;
 }
 
 static cos_status prepare_adjoint(cos_batch_t b) {
-    if (b->d_adj_ws) return COS_OK;
-    const int waves = std::max(b->nfs, b->nfs * std::max(1, 4 / b->nfs));
-    b->adj_block = 64 * waves;
-    int64_t total = 0;
-    for (auto &g : b->groups) {
-        const int64_t ws = (adj_ws_doubles(b->plans[g.first], b->nfs) + 31) & ~(int64_t)31;
-        const int64_t cap = std::max<int64_t>(1, kWorkspaceCap / (8 * ws));
-        const int gg = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)b->ncu * 2, (int64_t)g.second.second, cap}));
-        b->adj_ws.push_back(ws);
-        b->adj_grid.push_back(gg);
-        total = std::max(total, ws * gg);
+    if (b->d_Fall) return COS_OK;
+    int64_t fall = 0, gb = 0, sb = 0;
+    for (OrderGroup &o : b->orders) {
+        const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        const int64_t per_group = ((int64_t)o.hp->rows.size() + 2 * (int64_t)o.hp->max_rows) * rs;
+        o.chunk_adj = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
+        fall = std::max(fall, per_group * o.chunk_adj);
+        gb += (int64_t)o.ngroups * b->nfs * o.n * o.n * 64;
+        sb += (int64_t)o.ngroups * b->nfs * 64;
     }
-    if (hipMalloc((void **)&b->d_adj_ws, sizeof(double) * (size_t)total) != hipSuccess) {
-        b->d_adj_ws = nullptr;
-        b->adj_ws.clear();
-        b->adj_grid.clear();
-        return fail(COS_ENOMEM, "adjoint workspace allocation failed (%.1f MB)", 8.0 * total / 1e6);
+    if (hipMalloc((void **)&b->d_Fall, sizeof(double) * fall) != hipSuccess) {
+        b->d_Fall = nullptr;
+        return fail(COS_ENOMEM, "reverse-sweep workspace allocation failed (%.1f MB)", 8.0 * fall / 1e6);
     }
+    if (hipMalloc((void **)&b->d_GbT, sizeof(double) * gb) != hipSuccess ||
+        hipMalloc((void **)&b->d_sbT, sizeof(double) * sb) != hipSuccess) {
+        (void)hipFree(b->d_Fall);
+        (void)hipFree(b->d_GbT);
+        b->d_Fall = b->d_GbT = nullptr;
+        return fail(COS_ENOMEM, "gradient accumulator allocation failed");
+    }
+    b->fall_doubles = fall;
     return COS_OK;
 }
 
@@ -420,30 +475,58 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
     if (!d_out_bar || !d_G_bar) return fail(COS_EINVAL, "d_out_bar and d_G_bar are required");
     if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
     if ((st = prepare_adjoint(b))) return st;
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        const auto &g = b->groups[gi];
-        AdjArgs a;
-        std::memset(&a, 0, sizeof(a));
-        a.plan = b->plans[g.first];
-        a.order = b->d_order + g.second.first;
-        a.G = d_G;
-        a.Goff = d_Goff;
-        a.stub = (b->flags & COS_F_STUBS) ? d_stub : nullptr;
-        a.out_bar = d_out_bar;
-        a.out = d_out;
-        a.G_bar = d_G_bar;
-        a.stub_bar = (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr;
-        a.ws = b->d_adj_ws;
-        a.counter = b->d_counter;
-        a.ws_per_wg = b->adj_ws[gi];
-        a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
-        a.nconf = g.second.second;
-        a.nfs = b->nfs;
-        a.nmat = b->nmat;
-        a.nstub = b->nstub;
-        a.variant = b->variant;
-        a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
-        HIP_TRY(launch_adjoint(a, b->adj_grid[gi], b->adj_block, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    int64_t gb_off = 0, sb_off = 0;
+    for (const OrderGroup &o : b->orders) {
+        const PackArgs pa = pack_args(b, o, d_G, d_Goff, d_stub);
+        HIP_TRY(launch_pack(pa, s));
+        double *GbT = b->d_GbT + gb_off, *sbT = b->d_sbT + sb_off;
+        const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.n * o.n * 64, nsb = (int64_t)o.ngroups * b->nfs * 64;
+        HIP_TRY(launch_zero(GbT, ngb, s));
+        HIP_TRY(launch_zero(sbT, nsb, s));
+        const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        const int64_t total_rows = (int64_t)o.hp->rows.size();
+        const int64_t fstride = total_rows * rs, bstride = (int64_t)o.hp->max_rows * rs;
+        for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_adj) {
+            const int cg = std::min(o.chunk_adj, o.ngroups - c0);
+            double *Fall = b->d_Fall;
+            double *B0 = Fall + fstride * cg, *B1 = B0 + bstride * cg;
+            for (int l = 1; l <= 2 * o.n; ++l) {   // forward, every level kept
+                LvlArgs a = level_args(b, o, cycle_weight);
+                a.level = l;
+                a.group0 = c0;
+                a.cur = a.nxt = Fall;
+                a.cur_gstride = a.nxt_gstride = fstride;
+                a.cur_row0 = o.hp->levels[l].x;
+                a.nxt_row0 = o.hp->levels[std::min(l + 1, 2 * o.n + 1)].x;
+                const int nm = o.hp->levels[l].w;
+                a.mpb = masks_per_block(b->nfs, nm, cg, b->ncu);
+                a.out = d_out;
+                HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, s));
+            }
+            for (int l = 2 * o.n; l >= 1; --l) {   // reverse
+                LvlArgs a = level_args(b, o, cycle_weight);
+                a.level = l;
+                a.group0 = c0;
+                a.cur = (l & 1) ? B0 : B1;         // adjoints of level + 1
+                a.nxt = (l & 1) ? B1 : B0;         // adjoints of level
+                a.cur_gstride = a.nxt_gstride = bstride;
+                a.F = Fall;
+                a.F_gstride = fstride;
+                a.F_row0 = o.hp->levels[l].x;
+                const int nm = o.hp->levels[l].w;
+                // the reverse flushes its dS/dG accumulators once per block:
+                // larger blocks on big levels
+                a.mpb = masks_per_block(1, nm, cg, b->ncu, 32);
+                a.out_bar = d_out_bar;
+                a.Gbar_T = GbT;
+                a.sbar_T = sbT;
+                HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, s));
+            }
+        }
+        HIP_TRY(launch_unpack(pa, GbT, sbT, d_G_bar, (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr, s));
+        gb_off += ngb;
+        sb_off += nsb;
     }
     return COS_OK;
 }
