@@ -27,12 +27,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12           # MI355X FP64 vector peak, FLOP/s
+PEAK_HBM = 8.0e12             # MI355X HBM3E, bytes/s
+REV_KERNEL = "level_adj_kernel<%d>"
 WORKLOAD = "adjoint"
 
 
 def _kernel_hash():
     h = hashlib.sha256()
-    for f in ("cos_kernels.hip", "libcos.cpp", "cos_internal.hpp"):
+    for f in ("cos_level.hip", "cos_kernels.hip", "libcos.cpp", "cos_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2507_12349_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -85,6 +87,9 @@ def main():
     ap.add_argument("--nconf", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--counters", action="store_true",
+                    help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
+                         "then exit (for rocprofv3 --pmc passes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the configurations are independent and a "
@@ -118,31 +123,47 @@ def main():
     fwd_batch = B.Batch(d.n, w.nflav, 0, stubs=False)
     stream = torch.cuda.current_stream()
 
-    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for k in ("g0", "adj", "chain")}
-    acc = {k: 0.0 for k in ev}
-
-    def step(timed):
-        e = ev["g0"]
-        if timed: e[0].record(stream)
+    if args.counters:
+        # a plain copy of known size calibrates the HBM byte counters
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
         B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
-        if timed: e[1].record(stream); ev["adj"][0].record(stream)
+        fwd_batch.forward(G, geo.Goff, None, -1.0, S, stream)
         batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
-        if timed: ev["adj"][1].record(stream); ev["chain"][0].record(stream)
+        torch.cuda.synchronize()
+        print(json.dumps({"counters_pass": "done", "copy_bytes": 2 * 8 * (1 << 27)}), flush=True)
+        return
+
+    def evpair():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def step(e=None):
+        if e: e["g0"][0].record(stream)
+        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
+        if e: e["g0"][1].record(stream); e["adj"][0].record(stream)
+        batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
+        if e: e["adj"][1].record(stream); e["chain"][0].record(stream)
         B.chain_mu_shift(nconf, geo.n, 1, geo.Goff, Gb, dG, sb, 1, w.U, mub, alb, stream)
-        if timed: ev["chain"][1].record(stream)
+        if e: e["chain"][1].record(stream)
 
     for _ in range(args.warmup):
-        step(False)
+        step()
+    # per-step events (read after the timed region) and the library's phase
+    # events, all on the stream the kernels run on
+    evs = [{k: evpair() for k in ("g0", "adj", "chain")} for _ in range(args.steps)]
+    batch.timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step(True)
-        torch.cuda.synchronize()   # per-step sync so the per-kernel events can be read
-        for k, (a, b) in ev.items():
-            acc[k] += a.elapsed_time(b)
+    for i in range(args.steps):
+        step(evs[i])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    phases, ncalls = batch.timing_read()
+    batch.timing(False)
+    assert ncalls == args.steps
+    acc = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) for k in ("g0", "adj", "chain")}
     ms_step = 1e3 * wall / args.steps
     value = nconf / (wall / args.steps)
 
@@ -188,14 +209,26 @@ def main():
     plain_ms = pe0.elapsed_time(pe1)
     plain_equal = bool(torch.equal(Sp, S_batched))
 
-    # roofline of the dominant kernel (reverse sweep): algorithmic FLOP per
-    # configuration = 6 (E + C): forward recompute 2 (E + C), reverse 4 (E + C)
+    # roofline of the dominant kernel, the reverse level kernel: one launch
+    # per level, 2n launches per sweep; algorithmic FLOP of the sweep per
+    # configuration = 4 (E + C) (the adjoint of every extension and close
+    # edge: one FMA into B, one into dS/dG)
     pc = B.plan_counts(n)
     flop_fwd = 2.0 * (pc["ext"] + pc["closes"])
-    flop_adj = 3.0 * flop_fwd
-    adj_ms = acc["adj"] / args.steps
-    achieved = flop_adj * nconf / (adj_ms * 1e-3)
-    traffic = _traffic("adjoint_kernel<10,256>")
+    flop_rev = 2.0 * flop_fwd
+    nlaunch = 2 * n
+    rev_ms = phases["reverse"] / args.steps            # per sweep
+    launch_ms = rev_ms / nlaunch                       # average launch
+    flop_launch = flop_rev * nconf / nlaunch
+    achieved = flop_launch / (launch_ms * 1e-3)
+    traffic = _traffic(REV_KERNEL % n)
+    hbm = None
+    if traffic is not None:
+        ai = flop_launch / traffic
+        hbm = {"bytes_per_launch": traffic, "achieved_GBps": traffic / (launch_ms * 1e-3) / 1e9,
+               "frac_of_8TBps": traffic / (launch_ms * 1e-3) / PEAK_HBM,
+               "ai_flop_per_byte": ai,
+               "frac_of_attainable": achieved / min(PEAK_FP64, ai * PEAK_HBM)}
 
     cpu = None
     if not args.no_cpu:
@@ -221,18 +254,22 @@ def main():
         "config": {"workload": "adjoint: 8x8 lattice, beta=4, mu=-0.5, SU(4) uniform, n=10, "
                                "%d configs, forward + reverse sweep + chain rule to mu and shift" % nconf,
                    "n": n, "nflav": w.nflav, "nconf": nconf, "parallelism": "single GPU, persistent batched launch"},
-        "breakdown_ms": {"g0": acc["g0"] / args.steps, "adjoint_incl_forward": adj_ms,
-                         "chain": acc["chain"] / args.steps},
+        "breakdown_ms": {"g0": acc["g0"] / args.steps, "adjoint_incl_forward": acc["adj"] / args.steps,
+                         "chain": acc["chain"] / args.steps,
+                         "adjoint_phases": {k: v / args.steps for k, v in phases.items()}},
         "forward_batched_configs_per_s": nconf / (fwd_ms * 1e-3),
         "forward_kernel_ms": fwd_kernel_ms,
         "forward_plain_configs_per_s": nconf / (plain_ms * 1e-3),
         "batched_over_plain": (nconf / (fwd_ms * 1e-3)) / (nconf / (plain_ms * 1e-3)),
         "plain_equals_batched_bitwise": plain_equal,
-        "roofline": {"bound": "alu", "kernel": "adjoint_kernel<10,256> (reverse sweep with forward recompute)",
+        "roofline": {"bound": "alu", "kernel": REV_KERNEL % n,
+                     "unit_of_work": "one launch = one level of the reverse sweep over all %d configs "
+                                     "(%d launches per sweep; per-launch figures are sweep averages)" % (nconf, nlaunch),
                      "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64, "traffic": traffic,
-                     "flop_per_config": flop_adj,
-                     "forward_kernel_tflops": flop_fwd * nconf / (fwd_kernel_ms * 1e-3) / 1e12},
+                     "flop_per_launch": flop_launch, "avg_launch_ms": launch_ms,
+                     "flop_per_config_sweep": flop_rev, "hbm": hbm,
+                     "forward_kernel_tflops": flop_fwd * nconf / (phases["forward"] / args.steps * 1e-3) / 1e12},
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

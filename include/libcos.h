@@ -81,10 +81,11 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
 cos_status cos_batch_destroy(cos_batch_t b);
 
 /* Forward sum for every configuration of the batch, asynchronous on `stream`
- * (a hipStream_t, NULL = default stream).  One persistent launch per distinct
- * order in the batch (one launch when all orders are equal), largest order
- * first; each workgroup takes configurations from a work queue until none is
- * left.  No host synchronisation, no allocation: capturable in a graph.
+ * (a hipStream_t, NULL = default stream).  Configurations are packed 64 to a
+ * group (one per lane) by order, largest order first; for each order there is
+ * one launch per level of the state space (level = number of visited points,
+ * 2n levels), each covering every group of that order.  No host
+ * synchronisation, no allocation: capturable in a graph.
  * d_Goff may be NULL when the configurations are stored back to back.
  * d_stub is required iff the batch was planned with COS_F_STUBS.
  * Writes d_out[c] = S_c. */
@@ -139,6 +140,21 @@ cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat,
  * (a row = one (mask, head) pair). */
 cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
                            int64_t *shift_edges, int64_t *masks, int64_t *rows);
+
+/* Phase timing, a measurement aid.  After cos_batch_timing_enable(b, 1),
+ * every forward or adjoint call on b records HIP events on its own stream at
+ * the boundaries of its phases (COS_PHASE_*).  cos_batch_timing_read waits
+ * for the last recorded event, writes into ms[COS_NPHASES] the device time of
+ * each phase summed over every call since the previous read (milliseconds)
+ * and into *ncalls (may be NULL) the number of those calls, and starts a new
+ * accumulation.  Phases: packing of the inputs and zeroing of the gradient
+ * accumulators; the forward levels (recomputed inside the adjoint); the
+ * reverse levels; unpacking of the gradients.  Not for use under stream
+ * capture. */
+enum { COS_PHASE_PACK = 0, COS_PHASE_FORWARD = 1, COS_PHASE_REVERSE = 2, COS_PHASE_UNPACK = 3,
+       COS_NPHASES = 4 };
+cos_status cos_batch_timing_enable(cos_batch_t b, int32_t enable);
+cos_status cos_batch_timing_read(cos_batch_t b, double *ms, int32_t *ncalls);
 
 /* Diagnostics. */
 const char *cos_status_string(cos_status s);

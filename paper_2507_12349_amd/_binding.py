@@ -23,7 +23,9 @@ EXPORTED = (
     "cos_batch_create", "cos_batch_destroy", "cos_connected_sum_batched",
     "cos_connected_sum_adjoint", "cos_connected_sum", "cos_build_g0", "cos_chain_mu_shift",
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
+    "cos_batch_timing_enable", "cos_batch_timing_read",
 )
+PHASES = ("pack", "forward", "reverse", "unpack")
 
 
 def _load():
@@ -45,6 +47,8 @@ def _load():
         "cos_status_string": ([i32], ctypes.c_char_p),
         "cos_last_error": ([], ctypes.c_char_p),
         "cos_release": ([], i32),
+        "cos_batch_timing_enable": ([p, i32], i32),
+        "cos_batch_timing_read": ([p, ctypes.POINTER(d), ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -148,6 +152,19 @@ class Batch:
         _check(lib.cos_connected_sum_adjoint(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out_bar),
                                              _ptr(out), _ptr(G_bar), _ptr(stub_bar), _stream(stream)),
                "cos_connected_sum_adjoint")
+
+
+    def timing(self, enable: bool = True):
+        """Record HIP events at the phase boundaries of every later call."""
+        _check(lib.cos_batch_timing_enable(self._h, 1 if enable else 0), "cos_batch_timing_enable")
+
+    def timing_read(self):
+        """Device milliseconds per phase summed over the calls since the last
+        read (waits for them), and the number of calls."""
+        ms = (ctypes.c_double * len(PHASES))()
+        nc = ctypes.c_int32()
+        _check(lib.cos_batch_timing_read(self._h, ms, ctypes.byref(nc)), "cos_batch_timing_read")
+        return dict(zip(PHASES, list(ms))), nc.value
 
 
 def build_g0(nconf, n, voff, sites, tau, L, t, beta, mu, alpha, Goff, G, dG=None, stream=None):

@@ -75,6 +75,22 @@ __device__ __forceinline__ uint32_t lds_addr(double *p) {
     return (uint32_t)(uintptr_t)(lds_double *)p;
 }
 
+// a lane's word of a 64-wide slot: wave-uniform base + the lane's byte offset
+// (scalar base registers, one 32-bit offset register per lane)
+// (the empty asm pins the base in scalar registers, so that it is not folded
+// into a per-lane 64-bit address)
+typedef __attribute__((address_space(1))) char global_char;
+__device__ __forceinline__ double lane_ld(const double *base, uint32_t lane8) {
+    const global_char *p = (const global_char *)base;
+    asm volatile("" : "+s"(p));
+    return *(const __attribute__((address_space(1))) double *)(p + lane8);
+}
+__device__ __forceinline__ void lane_st(double *base, uint32_t lane8, double x) {
+    global_char *p = (global_char *)base;
+    asm volatile("" : "+s"(p));
+    *(__attribute__((address_space(1))) double *)(p + lane8) = x;
+}
+
 // ---------------------------------------------------------------------------
 // packing: caller layout -> per-lane layout (zeros in padding lanes)
 // ---------------------------------------------------------------------------
@@ -238,167 +254,142 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// reverse: B = dS/dF at level `level` from B at level + 1; dS/dG and
-// dS/dsigma accumulate per lane in registers and are added to the packed
-// accumulators at the end of the block.
+// reverse: B = dS/dF at level `level` from B at level + 1.
 //   a[w] = c_w B(m + e_w, u)[w] (open w) + [w == u] W tbar_m,
 //   tbar_m = sum_l B(m + e_h, h, l)[h] (1 at the full mask, 0 when dropped),
-//   B(m, u)[v] = sum_w G[v][w] a[w] + [m_v = 1, v current] (-sigma) a[v],
-//   Gbar[v][w] += f[v] a[w],  sigmabar += -f[w] B(m + e_w, u)[w] (shift edges).
+//   B(m, u)[v] = sum_w G[v][w] a[w] + [m_v = 1, v current] (-sigma) a'[v]
+//   (a' = a without the close term), Gbar[v][w] += f[v] a[w],
+//   sigmabar += -f[w] B(m + e_w, u)[w] on the shift edges.
+//
+// Every wavefront owns whole rows.  The dS/dG accumulator of the 64
+// configurations of the workgroup lives in LDS next to G ([v][w][lane], the
+// lanes add to consecutive words) and is added to the packed gradient once per
+// workgroup and flavour; only the (v, w) pairs a row can touch (v current,
+// w open or the head) are accumulated.
 // ---------------------------------------------------------------------------
-// one half of a row's reverse step: vertices v in [VLO, VHI) of B and of the
-// dS/dG rows; the other half runs on the partner wavefront
-template <int N, int VLO, int VHI>
-__device__ __forceinline__ void adj_block(const LvlArgs &A, const DevPlan &P, const int4 &L, int mb0, int mb1, int g,
-                                          const double *__restrict__ F, const double *__restrict__ Bn,
-                                          double *__restrict__ Bc, const double *tbw, uint32_t gaddr0, int lam) {
-    constexpr int NV = VHI - VLO;
-    const int nfs = A.nfs;
-    const int lane = threadIdx.x & 63;
-    double gacc[NV > 0 ? NV : 1][N];
+template <int N>
+__device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
+                                        const double *__restrict__ F, const double *__restrict__ Bn,
+                                        double *__restrict__ Bc, uint32_t lane8, int nfs, int lam, int u, int r,
+                                        bool start, double tb, double sgx, double sc, double &sacc) {
+    const uint32_t ones = M.ones, twos = M.twos;
+    const uint32_t cm = current_set(u, ones, twos);
+    const int v0 = cm ? __builtin_ctz(cm) : 0;   // every reachable row has a current; guard anyway
+    const double *__restrict__ src = F + ((int64_t)r * nfs + lam) * N * 64;
+    // every load is issued (the unused ones re-read a slot this row needs
+    // anyway) and the values are selected: straight-line code, no per-slot
+    // control flow joining whole arrays
+    double f[N], a[N];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
+    for (int v = 0; v < N; ++v) {
+        const bool c = (cm >> v) & 1u;
+        const double x = lane_ld(src + (c ? v : v0) * 64, lane8);
+        f[v] = start ? (v == 0 ? 1.0 : 0.0) : (c ? x : 0.0);   // start: (e_0, 0, 0) = 1
+    }
 #pragma unroll
-        for (int w = 0; w < N; ++w) gacc[v][w] = 0.0;
-    const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
-    double sacc = 0.0;
-    for (int mi = mb0; mi < mb1; ++mi) {
-        const MaskRec<N> M = load_rec<N>(P, L.z + mi);
-        const uint32_t ones = M.ones, twos = M.twos;
-        const int rb = M.rb;
-        const double sc = (M.code == 1 ? 2.0 : 1.0);
-        const double tb = tbw[(mi - mb0) * 64];
-        uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;
-        int u = 0, slot = 0;
-        while (true) {
-            const int r = rb + slot;
-            const uint32_t cm = current_set(u, ones, twos);
-            double f[NV > 0 ? NV : 1], a[N];
-            const double *__restrict__ src = F + ((int64_t)r * nfs + lam) * N * 64;
+    for (int w = 0; w < N; ++w) {
+        const uint32_t bit = 1u << w;
+        const bool open = !(twos & bit), first = !(ones & bit);
+        const int crow = open ? M.crb[w] + head_slot(u, first ? twos : (twos | bit)) : 0;
+        const double bc = lane_ld(Bn + (open ? ((int64_t)crow * nfs + lam) * N * 64 + w * 64 : 0), lane8);
+        a[w] = open ? (first ? 2.0 * bc : bc) : 0.0;
+        const bool shift = open && !first && (cm & bit);
+        sacc = shift ? __builtin_fma(-sc * f[w], bc, sacc) : sacc;
+    }
+    // the close of this row feeds t_m: dS/dacc[u] gains W tbar
 #pragma unroll
-            for (int v = VLO; v < VHI; ++v) f[v - VLO] = ((cm >> v) & 1u) ? src[v * 64] : 0.0;
-            if (A.level == 1) {
+    for (int w = 0; w < N; ++w) a[w] = (w == u) ? a[w] + tb : a[w];
+    const uint32_t need = (~twos | (1u << u)) & ((1u << N) - 1u);   // w with a[w] != 0 possible
+    asm volatile("" : "+v"(gaddr));
+    asm volatile("" : "+v"(gbaddr));
+    const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
+    lds_double *Gb = (lds_double *)(uintptr_t)gbaddr;
+    double *__restrict__ dst = Bc + ((int64_t)r * nfs + lam) * N * 64;
 #pragma unroll
-                for (int v = VLO; v < VHI; ++v) f[v - VLO] = v == 0 ? 1.0 : 0.0;
-            }
+    for (int v = 0; v < N; ++v) {
+        const uint32_t bit = 1u << v;
+        if (!(cm & bit)) continue;   // wave-uniform
+        double b = 0.0;
 #pragma unroll
-            for (int w = 0; w < N; ++w) {
-                const uint32_t bit = 1u << w;
-                a[w] = 0.0;
-                if (twos & bit) continue;
-                const bool first = !(ones & bit);
-                const uint32_t ctw = first ? twos : (twos | bit);
-                const int crow = M.crb[w] + head_slot(u, ctw);
-                const double bc = Bn[((int64_t)crow * nfs + lam) * N * 64 + w * 64];
-                a[w] = first ? 2.0 * bc : bc;
-                if (w >= VLO && w < VHI && !first && (cm & bit)) sacc = __builtin_fma(-sc * f[w - VLO], bc, sacc);
-            }
-            // the close of this row feeds t_m: dS/dacc[u] gains W tbar
-#pragma unroll
-            for (int w = 0; w < N; ++w)
-                if (w == u) a[w] += tb;
-            uint32_t gaddr = gaddr0;
-            asm volatile("" : "+v"(gaddr));
-            const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
-            double *__restrict__ dst = Bc + ((int64_t)r * nfs + lam) * N * 64;
-#pragma unroll
-            for (int v = VLO; v < VHI; ++v) {
-                double b = 0.0;
-#pragma unroll
-                for (int w = 0; w < N; ++w) b = __builtin_fma(Gs[(v * N + w) * 64], a[w], b);
-                const uint32_t bit = 1u << v;
-                if ((ones & bit) && (cm & bit)) {
-                    // shift edge out of this slot: child adjoint, without the close term
-                    const double bcv = (v == u) ? a[v] - tb : a[v];
-                    b = __builtin_fma(-sg * sc, bcv, b);
-                }
-                if (cm & bit) dst[v * 64] = b;
-            }
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int w = 0; w < N; ++w) gacc[v][w] = __builtin_fma(f[v], a[w], gacc[v][w]);
-            if (!hs) break;
-            u = __builtin_ctz(hs);
-            hs &= hs - 1u;
-            ++slot;
+        for (int w = 0; w < N; ++w) b = __builtin_fma(Gs[(v * N + w) * 64], a[w], b);
+        if (ones & bit) {
+            // shift edge out of this slot: child adjoint, without the close term
+            const double bcv = (v == u) ? a[v] - tb : a[v];
+            b = __builtin_fma(-sgx, bcv, b);
         }
-    }
-    if (mb0 < mb1) {
-        double *__restrict__ gb = A.Gbar_T + ((int64_t)(g * nfs + lam) * N * N) * 64 + lane;
+        lane_st(dst + v * 64, lane8, b);
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int w = 0; w < N; ++w) atomicAdd(gb + ((v + VLO) * N + w) * 64, gacc[v][w]);
-        if (A.stubs) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
+        for (int w = 0; w < N; ++w)
+            if (need & (1u << w))   // wave-uniform
+                __hip_atomic_fetch_add(Gb + (v * N + w) * 64, f[v] * a[w], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
-// slice k of SL equal parts of [0, N)
-template <int N, int SL, int K>
-struct Slice {
-    static constexpr int lo = K * N / SL, hi = (K + 1) * N / SL;
-};
-
-template <int N, int SL, int K>
-__device__ __forceinline__ void adj_slice(const LvlArgs &A, const DevPlan &P, const int4 &L, int mb0, int mb1, int g,
-                                          const double *__restrict__ F, const double *__restrict__ Bn,
-                                          double *__restrict__ Bc, const double *tbw, uint32_t gaddr0, int lam,
-                                          int k) {
-    if constexpr (K < SL) {
-        if (k == K)
-            adj_block<N, Slice<N, SL, K>::lo, Slice<N, SL, K>::hi>(A, P, L, mb0, mb1, g, F, Bn, Bc, tbw, gaddr0, lam);
-        else
-            adj_slice<N, SL, K + 1>(A, P, L, mb0, mb1, g, F, Bn, Bc, tbw, gaddr0, lam, k);
-    }
-}
-
-// reverse level kernel: SL wavefronts share a block of masks, one per slice
-// of the vertex range (fewer dS/dG accumulators per lane, more waves per SIMD)
-template <int N, int SL>
-__global__ void __launch_bounds__(512) level_adj_kernel(const LvlArgs A) {
+template <int N>
+__global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
-    double *Gs_all = lds;                     // [N * N][64]
-    double *tbs = lds + N * N * 64;           // [wpb / SL][mpb][64]: W * tbar per mask
+    double *Gs_all = lds;                     // [N * N][64]  G of the flavour
+    double *Gb_all = lds + N * N * 64;        // [N * N][64]  dS/dG of the flavour, this workgroup
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
-    const int team = wave / SL, slice = wave % SL;
-    const int nteams = (blockDim.x >> 6) / SL;
+    const int wpb = blockDim.x >> 6;
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
-    const int mb0 = (blockIdx.x * nteams + team) * A.mpb;
+    const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
     const int mb1 = min(mb0 + A.mpb, L.w);    // may be empty: the wave still joins the barriers
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
     const int64_t RS = (int64_t)nfs * N * 64;
-    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * RS + lane;
-    const double *__restrict__ Bn = A.cur + gl * A.cur_gstride + lane;   // level + 1
-    double *__restrict__ Bc = A.nxt + gl * A.nxt_gstride + lane;         // level
+    // wave-uniform bases; the lane's word is added at each access
+    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * RS;
+    const double *__restrict__ Bn = A.cur + gl * A.cur_gstride;   // level + 1
+    double *__restrict__ Bc = A.nxt + gl * A.nxt_gstride;         // level
+    const uint32_t lane8 = (uint32_t)lane * 8u;
     const int cfg = A.lane_cfg[g * 64 + lane];
     const double obar = cfg >= 0 ? A.out_bar[cfg] : 0.0;
-    const uint32_t gaddr0 = lds_addr(Gs_all) + lane * 8u;
-    double *tbw = tbs + (size_t)team * A.mpb * 64 + lane;
+    const uint32_t gaddr = lds_addr(Gs_all) + lane * 8u, gbaddr = lds_addr(Gb_all) + lane * 8u;
+    const bool top = A.level == 2 * N, start = A.level == 1;
 
-    if (slice == 0) {
+    for (int lam = 0; lam < nfs; ++lam) {
+        __syncthreads();   // the previous flavour's accumulator has been flushed
+        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * N * N * 64;
+        for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
+            Gs_all[i] = gsrc[i];
+            Gb_all[i] = 0.0;
+        }
+        __syncthreads();
+        const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
+        double sacc = 0.0;
         for (int mi = mb0; mi < mb1; ++mi) {
             const MaskRec<N> M = load_rec<N>(P, L.z + mi);
             const uint32_t ones = M.ones, twos = M.twos;
             double tb = 0.0;
-            if (A.level == 2 * N) {
+            if (top) {
                 tb = obar;
             } else if (ones) {
                 const int h = __builtin_ctz(ones);
                 const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
-                for (int kk = 0; kk < nfs; ++kk) tb += Bn[((int64_t)crow * nfs + kk) * N * 64 + h * 64];
+                for (int k = 0; k < nfs; ++k) tb += lane_ld(Bn + ((int64_t)crow * nfs + k) * N * 64 + h * 64, lane8);
             }
-            tbw[(mi - mb0) * 64] = A.W * tb;
+            tb *= A.W;
+            const double sc = (M.code == 1 ? 2.0 : 1.0);
+            uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
+            int u = 0, slot = 0;
+            while (true) {
+                adj_row<N>(M, gaddr, gbaddr, F, Bn, Bc, lane8, nfs, lam, u, M.rb + slot, start, tb, sg * sc, sc, sacc);
+                if (!hs) break;
+                u = __builtin_ctz(hs);
+                hs &= hs - 1u;
+                ++slot;
+            }
         }
-    }
-    for (int lam = 0; lam < nfs; ++lam) {
-        __syncthreads();   // also publishes tbar of the first wave of each team
-        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * N * N * 64;
-        for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) Gs_all[i] = gsrc[i];
+        if (A.stubs && mb0 < mb1) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
         __syncthreads();
-        adj_slice<N, SL, 0>(A, P, L, mb0, mb1, g, F, Bn, Bc, tbw, gaddr0, lam, slice);
+        double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * N * N * 64;
+        for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
+            const double x = Gb_all[i];
+            if (x != 0.0) atomicAdd(gb + i, x);
+        }
     }
 }
 
@@ -448,8 +439,9 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
 }
 
 int fwd_waves_per_block() { return 8; }
-// wavefronts sharing one row in the reverse sweep (slices of the vertex range)
-int adj_slices(int n) { return n >= 8 ? 4 : 2; }
+// the reverse sweep shares one LDS accumulator among the wavefronts of a
+// workgroup: large workgroups
+int adj_waves_per_block() { return 16; }
 
 // raise a kernel's dynamic-LDS limit when a launch needs more than 64 KB
 static hipError_t allow_lds(const void *fn, size_t bytes) {
@@ -461,21 +453,20 @@ hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups
     const int n = a.plan.n;
     const int wpb = fwd_waves_per_block();
     if (reverse) {
-        const int sl = adj_slices(n);
-        const int nteams = wpb / sl;
-        const size_t shm = (size_t)n * n * 64 * sizeof(double) + (size_t)nteams * a.mpb * 64 * sizeof(double);
-        const dim3 grid((unsigned)((nblocks + nteams - 1) / nteams), (unsigned)ngroups);
+        const int wpa = adj_waves_per_block();
+        const size_t shm = 2 * (size_t)n * n * 64 * sizeof(double);
+        const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups);
         switch (n) {
-#define COS_ADJ_CASE(K, SLK)                                                              \
-    case K: {                                                                             \
-        hipError_t e = allow_lds((const void *)level_adj_kernel<K, SLK>, shm);            \
-        if (e != hipSuccess) return e;                                                    \
-        hipLaunchKernelGGL((level_adj_kernel<K, SLK>), grid, dim3(64 * wpb), shm, s, a);  \
-        break;                                                                            \
+#define COS_ADJ_CASE(K)                                                              \
+    case K: {                                                                        \
+        hipError_t e = allow_lds((const void *)level_adj_kernel<K>, shm);            \
+        if (e != hipSuccess) return e;                                               \
+        hipLaunchKernelGGL((level_adj_kernel<K>), grid, dim3(64 * wpa), shm, s, a);  \
+        break;                                                                       \
     }
-            COS_ADJ_CASE(1, 2) COS_ADJ_CASE(2, 2) COS_ADJ_CASE(3, 2) COS_ADJ_CASE(4, 2)
-            COS_ADJ_CASE(5, 2) COS_ADJ_CASE(6, 2) COS_ADJ_CASE(7, 2) COS_ADJ_CASE(8, 4)
-            COS_ADJ_CASE(9, 4) COS_ADJ_CASE(10, 4) COS_ADJ_CASE(11, 4) COS_ADJ_CASE(12, 4)
+            COS_ADJ_CASE(1) COS_ADJ_CASE(2) COS_ADJ_CASE(3) COS_ADJ_CASE(4)
+            COS_ADJ_CASE(5) COS_ADJ_CASE(6) COS_ADJ_CASE(7) COS_ADJ_CASE(8)
+            COS_ADJ_CASE(9) COS_ADJ_CASE(10) COS_ADJ_CASE(11) COS_ADJ_CASE(12)
 #undef COS_ADJ_CASE
             default: return hipErrorInvalidValue;
         }

@@ -232,7 +232,30 @@ struct cos_batch_s {
     // reverse sweep (allocated on first use)
     double *d_Fall = nullptr, *d_GbT = nullptr, *d_sbT = nullptr;
     int64_t fall_doubles = 0;
+    // phase timing: events recorded at phase boundaries since the last read,
+    // each labelled with the phase that starts there (-1: end of a call)
+    bool timing = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_phase;
 };
+
+namespace {
+
+// start of `phase` (or, with -1, the end of a call) on stream s
+hipError_t tmark(cos_batch_s *b, int phase, hipStream_t s) {
+    if (!b->timing) return hipSuccess;
+    const size_t k = b->ev_phase.size();
+    if (k == b->ev.size()) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        b->ev.push_back(e);
+    }
+    b->ev_phase.push_back(phase);
+    return hipEventRecord(b->ev[k], s);
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -352,6 +375,7 @@ cos_status cos_batch_destroy(cos_batch_t b) {
     (void)hipFree(b->d_Fall);
     (void)hipFree(b->d_GbT);
     (void)hipFree(b->d_sbT);
+    for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     delete b;
     return COS_OK;
 }
@@ -409,6 +433,15 @@ static int masks_per_block(int nfs, int nm, int ng, int ncu, int cap1 = 8) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, per));
 }
 
+// masks per wavefront of the reverse sweep: one workgroup (16 wavefronts,
+// one per CU by its LDS footprint) flushes its dS/dG accumulator once per
+// flavour, so blocks should be large, but a level needs several workgroups per
+// CU or its last round leaves most of the chip idle
+static int adj_masks_per_wave(int nm, int ng, int ncu) {
+    const int64_t per = ((int64_t)nm * ng) / std::max<int64_t>(1, (int64_t)ncu * 16 * 4);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8, per));
+}
+
 cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
                                      const double *d_stub, double cycle_weight, double *d_out,
                                      void *stream) {
@@ -417,7 +450,9 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
     hipStream_t s = (hipStream_t)stream;
     for (const OrderGroup &o : b->orders) {
+        HIP_TRY(tmark(b, COS_PHASE_PACK, s));
         HIP_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
+        HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
         const int64_t rs = (int64_t)b->nfs * o.n * 64;
         const int64_t gstride = (int64_t)o.hp->max_rows * rs;
         for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_fwd) {
@@ -437,6 +472,7 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
             }
         }
     }
+    HIP_TRY(tmark(b, -1, s));
     return COS_OK;
 }
 
@@ -479,6 +515,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
     int64_t gb_off = 0, sb_off = 0;
     for (const OrderGroup &o : b->orders) {
         const PackArgs pa = pack_args(b, o, d_G, d_Goff, d_stub);
+        HIP_TRY(tmark(b, COS_PHASE_PACK, s));
         HIP_TRY(launch_pack(pa, s));
         double *GbT = b->d_GbT + gb_off, *sbT = b->d_sbT + sb_off;
         const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.n * o.n * 64, nsb = (int64_t)o.ngroups * b->nfs * 64;
@@ -491,6 +528,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
             const int cg = std::min(o.chunk_adj, o.ngroups - c0);
             double *Fall = b->d_Fall;
             double *B0 = Fall + fstride * cg, *B1 = B0 + bstride * cg;
+            HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
             for (int l = 1; l <= 2 * o.n; ++l) {   // forward, every level kept
                 LvlArgs a = level_args(b, o, cycle_weight);
                 a.level = l;
@@ -504,6 +542,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
                 a.out = d_out;
                 HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, s));
             }
+            HIP_TRY(tmark(b, COS_PHASE_REVERSE, s));
             for (int l = 2 * o.n; l >= 1; --l) {   // reverse
                 LvlArgs a = level_args(b, o, cycle_weight);
                 a.level = l;
@@ -515,19 +554,46 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
                 a.F_gstride = fstride;
                 a.F_row0 = o.hp->levels[l].x;
                 const int nm = o.hp->levels[l].w;
-                // the reverse flushes its dS/dG accumulators once per block:
-                // larger blocks on big levels
-                a.mpb = masks_per_block(1, nm, cg, b->ncu, 32);
+                a.mpb = adj_masks_per_wave(nm, cg, b->ncu);
                 a.out_bar = d_out_bar;
                 a.Gbar_T = GbT;
                 a.sbar_T = sbT;
                 HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, s));
             }
         }
+        HIP_TRY(tmark(b, COS_PHASE_UNPACK, s));
         HIP_TRY(launch_unpack(pa, GbT, sbT, d_G_bar, (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr, s));
         gb_off += ngb;
         sb_off += nsb;
     }
+    HIP_TRY(tmark(b, -1, s));
+    return COS_OK;
+}
+
+cos_status cos_batch_timing_enable(cos_batch_t b, int32_t enable) {
+    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    b->timing = enable != 0;
+    b->ev_phase.clear();
+    return COS_OK;
+}
+
+cos_status cos_batch_timing_read(cos_batch_t b, double *ms, int32_t *ncalls) {
+    if (!b || !ms) return fail(COS_EINVAL, "batch handle and ms are required");
+    for (int p = 0; p < COS_NPHASES; ++p) ms[p] = 0.0;
+    int32_t calls = 0;
+    const size_t k = b->ev_phase.size();
+    if (k) HIP_TRY(hipEventSynchronize(b->ev[k - 1]));
+    for (size_t i = 0; i < k; ++i) {
+        if (b->ev_phase[i] < 0 || i + 1 == k) {
+            ++calls;
+            continue;
+        }
+        float t = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&t, b->ev[i], b->ev[i + 1]));
+        ms[b->ev_phase[i]] += t;
+    }
+    b->ev_phase.clear();
+    if (ncalls) *ncalls = calls;
     return COS_OK;
 }
 

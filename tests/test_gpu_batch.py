@@ -113,3 +113,34 @@ def test_autograd_function_matches_adjoint():
     ref = np.concatenate([x.reshape(-1) for x in gb])
     assert np.allclose(G.grad.cpu().numpy(), ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
     b.close()
+
+
+def test_phase_timing():
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("phase timing events, 2 adjoint calls + 1 forward, orders 6 and 8")
+    rng = np.random.default_rng(11)
+    mats = [rng.normal(size=(1, n, n)) * 0.5 for n in (6, 8, 6, 8, 8)]
+    flat, off, n = pack(mats)
+    b = B.Batch(n, 2, 0)
+    G, Goff = _dev(flat), _dev(off)
+    out = torch.empty(len(mats), dtype=torch.float64, device="cuda:0")
+    Gb = torch.empty_like(G)
+    b.timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(2):
+        b.adjoint(G, Goff, None, -1.0, torch.ones_like(out), out, Gb, None)
+    b.forward(G, Goff, None, -1.0, out)
+    e1.record()
+    ms, calls = b.timing_read()
+    torch.cuda.synchronize()
+    assert calls == 3
+    assert all(v >= 0.0 for v in ms.values())
+    assert ms["forward"] > 0.0 and ms["reverse"] > 0.0 and ms["pack"] > 0.0 and ms["unpack"] > 0.0
+    # the phases cover the calls: their sum cannot exceed the bracketing events
+    assert sum(ms.values()) <= e0.elapsed_time(e1) * 1.01 + 0.05
+    ms2, calls2 = b.timing_read()
+    assert calls2 == 0 and sum(ms2.values()) == 0.0
+    b.timing(False)
+    b.close()
