@@ -141,6 +141,24 @@ cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat,
 cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
                            int64_t *shift_edges, int64_t *masks, int64_t *rows);
 
+/* Autotuner (Results, GPU parallelization: launch shape per problem size).
+ * For every order in the batch, times the level kernels over the caller's
+ * inputs for each candidate launch shape -- wavefronts per workgroup of the
+ * forward kernel (4, 8) and the most masks (state-table tiles) per wavefront
+ * (1, 2, 4, 8, 16) of the forward and, when d_out_bar is not NULL, of the
+ * reverse kernel -- keeps the fastest per order and uses it for every later
+ * call on b.  Arguments as cos_connected_sum_batched / _adjoint; the output
+ * buffers are overwritten and on return hold what a call with the chosen
+ * shapes writes.  Synchronous (waits for the stream).  S does not depend on
+ * the launch shape (bitwise); the gradients do only through the summation
+ * order of their accumulation. */
+cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
+                              const double *d_stub, double cycle_weight, const double *d_out_bar,
+                              double *d_out, double *d_G_bar, double *d_stub_bar, void *stream);
+/* The launch shape in use for order n (COS_EINVAL if the batch has none). */
+cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves,
+                                  int32_t *fwd_masks, int32_t *adj_masks);
+
 /* Phase timing, a measurement aid.  After cos_batch_timing_enable(b, 1),
  * every forward or adjoint call on b records HIP events on its own stream at
  * the boundaries of its phases (COS_PHASE_*).  cos_batch_timing_read waits

@@ -23,7 +23,7 @@ EXPORTED = (
     "cos_batch_create", "cos_batch_destroy", "cos_connected_sum_batched",
     "cos_connected_sum_adjoint", "cos_connected_sum", "cos_build_g0", "cos_chain_mu_shift",
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
-    "cos_batch_timing_enable", "cos_batch_timing_read",
+    "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -32,6 +32,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libcos.so is not built (%s); run __graft_entry__.build() or "
                           "python paper_2507_12349_amd/csrc/build.py" % LIB_PATH)
+    # torch ships its own HIP runtime with the same soname as the system one;
+    # loading torch first makes libcos bind to that runtime, so that the
+    # library and torch's tensors and streams share one runtime per process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     i32, i64, d, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
     P64 = ctypes.POINTER(ctypes.c_int64)
@@ -49,6 +53,8 @@ def _load():
         "cos_release": ([], i32),
         "cos_batch_timing_enable": ([p, i32], i32),
         "cos_batch_timing_read": ([p, ctypes.POINTER(d), ctypes.POINTER(i32)], i32),
+        "cos_batch_autotune": ([p, p, p, p, d, p, p, p, p, p], i32),
+        "cos_batch_launch_shape": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -153,6 +159,17 @@ class Batch:
                                              _ptr(out), _ptr(G_bar), _ptr(stub_bar), _stream(stream)),
                "cos_connected_sum_adjoint")
 
+
+    def autotune(self, G, Goff, stub, w, out, out_bar=None, G_bar=None, stub_bar=None, stream=None):
+        """Pick the fastest launch shape per order on these inputs (synchronous);
+        with out_bar the reverse sweep is tuned too."""
+        _check(lib.cos_batch_autotune(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out_bar), _ptr(out),
+                                      _ptr(G_bar), _ptr(stub_bar), _stream(stream)), "cos_batch_autotune")
+
+    def launch_shape(self, n: int):
+        vals = [ctypes.c_int32() for _ in range(3)]
+        _check(lib.cos_batch_launch_shape(self._h, int(n), *[ctypes.byref(v) for v in vals]), "cos_batch_launch_shape")
+        return dict(zip(("fwd_waves", "fwd_masks", "adj_masks"), [v.value for v in vals]))
 
     def timing(self, enable: bool = True):
         """Record HIP events at the phase boundaries of every later call."""

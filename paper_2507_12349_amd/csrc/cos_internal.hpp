@@ -35,6 +35,7 @@ namespace libcos {
 //   [3 + w] level-relative row of (m + e_w, 0) for each vertex w with m_w < 2
 //           (-1 otherwise)
 constexpr int kRecInts = 16;
+static_assert(3 + COS_NMAX <= kRecInts, "mask record too small");
 
 struct DevPlan {
     const int32_t *mrec;      // [total_masks][kRecInts]
@@ -102,7 +103,12 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_unpack(const PackArgs &a, const double *GbT, const double *sbT, double *Gb, double *sb,
                          hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
-hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, hipStream_t s);
+// nblocks = blocks of `a.mpb` masks; `wpb` wavefronts per workgroup (forward:
+// at most 8; the reverse kernel always runs adj_waves_per_block())
+hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s);
+int adj_waves_per_block();
+// most masks per wavefront of the forward kernel when there are several flavours
+constexpr int kMultiMasks = 4;
 // launchers (cos_kernels.hip)
 hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int32_t *sites,
                      const double *tau, int L, double t, double beta, int nmat, const double *mu,

@@ -132,8 +132,8 @@ __global__ void pack_kernel(const PackArgs A) {
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
-                                        double *__restrict__ nxt, int nfs, int lam, int u, int r, bool start,
-                                        double sgx, double &cp, double &dext) {
+                                        double *__restrict__ nxt, uint32_t lane8, int nfs, int lam, int u, int r,
+                                        bool start, double sgx, double &cp, double &dext) {
     const uint32_t ones = M.ones, twos = M.twos;
     const uint32_t cm = current_set(u, ones, twos);
     const double *__restrict__ src = cur + ((int64_t)r * nfs + lam) * N * 64;
@@ -141,12 +141,17 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
     // the row instead of hoisted into N^2 registers for the whole loop
     asm volatile("" : "+v"(gaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
+    // only current slots are loaded (the row's dense product is cheaper than
+    // skipping the zero rows of f: measured)
     double f[N], acc[N];
 #pragma unroll
-    for (int v = 0; v < N; ++v) f[v] = ((cm >> v) & 1u) ? src[v * 64] : 0.0;
+    for (int v = 0; v < N; ++v) {
+        const bool c = (cm >> v) & 1u;
+        f[v] = c ? lane_ld(src + v * 64, lane8) : 0.0;
+    }
     if (start) {
 #pragma unroll
-        for (int v = 0; v < N; ++v) f[v] = v == 0 ? 1.0 : 0.0;   // start: (e_0, 0, 0) = 1
+        for (int v = 0; v < N; ++v) f[v] = v == 0 ? 1.0 : 0.0;
     }
 #pragma unroll
     for (int w = 0; w < N; ++w) acc[w] = 0.0;
@@ -170,23 +175,24 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
         }
         const uint32_t ctw = first ? twos : (twos | bit);
         const int crow = M.crb[w] + head_slot(u, ctw);
-        nxt[((int64_t)crow * nfs + lam) * N * 64 + w * 64] = val;
+        lane_st(nxt + ((int64_t)crow * nfs + lam) * N * 64 + w * 64, lane8, val);
     }
 }
 
 template <int N>
-__device__ __forceinline__ void fwd_close(const MaskRec<N> &M, double *__restrict__ nxt, int nfs, int lam, double t,
-                                          double dext) {
+__device__ __forceinline__ void fwd_close(const MaskRec<N> &M, double *__restrict__ nxt, uint32_t lane8, int nfs,
+                                          int lam, double t, double dext) {
     const int h = __builtin_ctz(M.ones);
     const int crow = close_row_base<N>(M, h) + head_slot(h, M.twos | (1u << h));
-    nxt[((int64_t)crow * nfs + lam) * N * 64 + h * 64] = t + (h == 0 ? dext : 0.0);
+    lane_st(nxt + ((int64_t)crow * nfs + lam) * N * 64 + h * 64, lane8, t + (h == 0 ? dext : 0.0));
 }
 
+// with several flavours (kMultiMasks masks per wavefront at most) the close
+// sums of the wave's masks stay in registers across the flavour loop
 template <int N, bool MULTI>
 __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
     double *Gs_all = lds;                      // [N * N][64]
-    double *cs = lds + N * N * 64;             // MULTI: [wpb][mpb][nfs + 1][64]
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
     const DevPlan &P = A.plan;
@@ -196,14 +202,17 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
     const int64_t RS = (int64_t)nfs * N * 64;
-    const double *__restrict__ cur = A.cur + gl * A.cur_gstride + (int64_t)A.cur_row0 * RS + lane;
-    double *__restrict__ nxt = A.nxt + gl * A.nxt_gstride + (int64_t)A.nxt_row0 * RS + lane;
+    // wave-uniform bases; the lane's word is added at each access
+    const double *__restrict__ cur = A.cur + gl * A.cur_gstride + (int64_t)A.cur_row0 * RS;
+    double *__restrict__ nxt = A.nxt + gl * A.nxt_gstride + (int64_t)A.nxt_row0 * RS;
+    const uint32_t lane8 = (uint32_t)lane * 8u;
     const uint32_t gaddr = lds_addr(Gs_all) + lane * 8u;
     const int cfg = A.lane_cfg[g * 64 + lane];
     const bool last = A.level == 2 * N, start = A.level == 1;
-    double *csw = cs + (size_t)wave * A.mpb * (nfs + 1) * 64 + lane;
-    if (MULTI)
-        for (int i = 0; i < (mb1 - mb0) * (nfs + 1); ++i) csw[i * 64] = 0.0;
+    constexpr int K = MULTI ? kMultiMasks : 1;
+    double cpk[K];   // MULTI: close sum of each of the wave's masks, over heads and flavours
+#pragma unroll
+    for (int k = 0; k < K; ++k) cpk[k] = 0.0;
 
     for (int lam = 0; lam < nfs; ++lam) {
         __syncthreads();
@@ -211,43 +220,59 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
         for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) Gs_all[i] = gsrc[i];
         __syncthreads();
         const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
-        for (int mi = mb0; mi < mb1; ++mi) {
-            const MaskRec<N> M = load_rec<N>(P, L.z + mi);
-            const uint32_t ones = M.ones, twos = M.twos;
-            const double sgx = sg * (M.code == 1 ? 2.0 : 1.0);
-            uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
-            int u = 0, slot = 0;
-            double cp = 0.0, dext = 0.0;
-            while (true) {
-                fwd_row<N>(M, gaddr, cur, nxt, nfs, lam, u, M.rb + slot, start, sgx, cp, dext);
-                if (!hs) break;
-                u = __builtin_ctz(hs);
-                hs &= hs - 1u;
-                ++slot;
-            }
-            if (MULTI) {
-                double *c = csw + (size_t)(mi - mb0) * (nfs + 1) * 64;
-                c[0] += cp;
-                c[(1 + lam) * 64] = dext;
-            } else {
-                const double t = A.W * cp;
-                if (last) {
-                    if (cfg >= 0 && A.out) A.out[cfg] = t;
-                } else if (ones) {
-                    fwd_close<N>(M, nxt, nfs, 0, t, dext);
+        // MULTI: at most K masks, unrolled so that cpk stays in registers
+        const int mend = MULTI ? min(mb1, mb0 + K) : mb1;
+#pragma unroll
+        for (int k = 0; k < (MULTI ? K : 1); ++k) {
+            for (int mi = mb0 + k; mi < mend; mi += (MULTI ? K : 1)) {
+                const MaskRec<N> M = load_rec<N>(P, L.z + mi);
+                const uint32_t ones = M.ones, twos = M.twos;
+                const double sgx = sg * (M.code == 1 ? 2.0 : 1.0);
+                uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
+                int u = 0, slot = 0;
+                double cp = 0.0, dext = 0.0;
+                while (true) {
+                    fwd_row<N>(M, gaddr, cur, nxt, lane8, nfs, lam, u, M.rb + slot, start, sgx, cp, dext);
+                    if (!hs) break;
+                    u = __builtin_ctz(hs);
+                    hs &= hs - 1u;
+                    ++slot;
+                }
+                if (MULTI) {
+                    cpk[k] += cp;
+                    // m_0 = 1 (so h = 0): this flavour's extension into the slot
+                    // the next cycle opens on; the close adds to it at the end
+                    if (!last && (ones & 1u)) fwd_close<N>(M, nxt, lane8, nfs, lam, 0.0, dext);
+                } else {
+                    const double t = A.W * cp;
+                    if (last) {
+                        if (cfg >= 0 && A.out) A.out[cfg] = t;
+                    } else if (ones) {
+                        fwd_close<N>(M, nxt, lane8, nfs, 0, t, dext);
+                    }
                 }
             }
         }
     }
     if (MULTI) {
-        for (int mi = mb0; mi < mb1; ++mi) {
+        // t_m = W sum over heads and flavours; the next cycle opens in every flavour
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int mi = mb0 + k;
+            if (mi >= mb1) continue;
             const MaskRec<N> M = load_rec<N>(P, L.z + mi);
-            const double *c = csw + (size_t)(mi - mb0) * (nfs + 1) * 64;
-            const double t = A.W * c[0];
+            const double t = A.W * cpk[k];
             if (last) {
                 if (cfg >= 0 && A.out) A.out[cfg] = t;
             } else if (M.ones) {
-                for (int lam = 0; lam < nfs; ++lam) fwd_close<N>(M, nxt, nfs, lam, t, c[(1 + lam) * 64]);
+                const int h = __builtin_ctz(M.ones);
+                const int crow = close_row_base<N>(M, h) + head_slot(h, M.twos | (1u << h));
+                double *dst = nxt + (int64_t)crow * nfs * N * 64 + h * 64;
+                for (int lam = 0; lam < nfs; ++lam) {
+                    // h = 0: the slot holds this wave's own extension value (written above)
+                    const double x = h == 0 ? lane_ld(dst + lam * N * 64, lane8) : 0.0;
+                    lane_st(dst + lam * N * 64, lane8, t + x);
+                }
             }
         }
     }
@@ -438,7 +463,6 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
     return hipGetLastError();
 }
 
-int fwd_waves_per_block() { return 8; }
 // the reverse sweep shares one LDS accumulator among the wavefronts of a
 // workgroup: large workgroups
 int adj_waves_per_block() { return 16; }
@@ -449,9 +473,9 @@ static hipError_t allow_lds(const void *fn, size_t bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, hipStream_t s) {
+hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s) {
     const int n = a.plan.n;
-    const int wpb = fwd_waves_per_block();
+    if (!reverse && (wpb < 1 || wpb > 8)) return hipErrorInvalidValue;
     if (reverse) {
         const int wpa = adj_waves_per_block();
         const size_t shm = 2 * (size_t)n * n * 64 * sizeof(double);
@@ -473,8 +497,8 @@ hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups
         return hipGetLastError();
     }
     const bool multi = a.nfs > 1;
-    const size_t shm = (size_t)n * n * 64 * sizeof(double) +
-                       (multi ? (size_t)wpb * a.mpb * (a.nfs + 1) * 64 * sizeof(double) : 0);
+    if (multi && a.mpb > kMultiMasks) return hipErrorInvalidValue;
+    const size_t shm = (size_t)n * n * 64 * sizeof(double);
     const dim3 grid((unsigned)((nblocks + wpb - 1) / wpb), (unsigned)ngroups);
     switch (n) {
 #define COS_FWD_CASE(K)                                                                                    \

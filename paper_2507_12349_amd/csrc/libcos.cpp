@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -208,12 +209,21 @@ cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
 
 }  // namespace
 
+// launch shape of the level kernels of one order
+struct LaunchShape {
+    int fwd_wpb = 8;    // forward: wavefronts per workgroup (<= 8)
+    int fwd_cap = 0;    // forward: most masks per wavefront (0: by flavour count)
+    int adj_cap = 8;    // reverse: most masks per wavefront
+};
+
 // all configurations of one order inside a batch
 struct OrderGroup {
     int n = 0, first = 0, count = 0;   // configurations d_order[first .. first + count)
     int ngroups = 0;                   // 64 configurations per group (one per lane)
     int64_t gt_off = 0, sig_off = 0, lane_off = 0;   // offsets into the packed buffers
     int chunk_fwd = 1, chunk_adj = 1;  // groups per chunk (bounded workspace)
+    int64_t gb_off = 0, sb_off = 0;    // offsets into the packed gradient accumulators
+    LaunchShape shape;                 // launch shape of the level kernels (autotuned)
     std::shared_ptr<HostPlan> hp;
 };
 
@@ -423,23 +433,50 @@ static LvlArgs level_args(cos_batch_t b, const OrderGroup &o, double cycle_weigh
     return a;
 }
 
-// masks per wavefront for a level of `nm` masks and `ng` groups: up to `cap1`
-// (to amortise loading G into LDS and flushing accumulators), fewer when the
-// level is small so that its rows spread over enough wavefronts
-static int masks_per_block(int nfs, int nm, int ng, int ncu, int cap1 = 8) {
-    const int cap = nfs <= 1 ? cap1 : std::max(2, 16 / (nfs + 1));
-    const int64_t want_waves = (int64_t)ncu * 16;
-    const int64_t per = ((int64_t)nm * ng) / std::max<int64_t>(1, want_waves);
+// masks per wavefront of a forward level launch with `nm` masks and `ng`
+// groups: up to the shape's cap (to amortise loading G into LDS), fewer when
+// the level is small so that its rows spread over enough wavefronts
+static int fwd_masks(const LaunchShape &sh, int nfs, int nm, int ng, int ncu) {
+    int cap = sh.fwd_cap ? sh.fwd_cap : (nfs <= 1 ? 8 : kMultiMasks);
+    if (nfs > 1) cap = std::min(cap, kMultiMasks);   // close sums of several flavours in registers
+    const int64_t per = ((int64_t)nm * ng) / std::max<int64_t>(1, (int64_t)ncu * 16);
     return (int)std::max<int64_t>(1, std::min<int64_t>(cap, per));
 }
 
-// masks per wavefront of the reverse sweep: one workgroup (16 wavefronts,
-// one per CU by its LDS footprint) flushes its dS/dG accumulator once per
-// flavour, so blocks should be large, but a level needs several workgroups per
-// CU or its last round leaves most of the chip idle
-static int adj_masks_per_wave(int nm, int ng, int ncu) {
+// masks per wavefront of a reverse level launch: one workgroup (16
+// wavefronts, one per CU by its LDS footprint) flushes its dS/dG accumulator
+// once per flavour, so blocks should be large, but a level needs several
+// workgroups per CU or its last round leaves most of the chip idle
+static int adj_masks(const LaunchShape &sh, int nm, int ng, int ncu) {
     const int64_t per = ((int64_t)nm * ng) / std::max<int64_t>(1, (int64_t)ncu * 16 * 4);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(8, per));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sh.adj_cap, per));
+}
+
+// forward levels of one order, all groups, chunk by chunk (two level windows)
+static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double *d_G, const int64_t *d_Goff,
+                                const double *d_stub, double cycle_weight, double *d_out, hipStream_t s) {
+    HIP_TRY(tmark(b, COS_PHASE_PACK, s));
+    HIP_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
+    HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
+    const int64_t rs = (int64_t)b->nfs * o.n * 64;
+    const int64_t gstride = (int64_t)o.hp->max_rows * rs;
+    for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_fwd) {
+        const int cg = std::min(o.chunk_fwd, o.ngroups - c0);
+        double *win0 = b->d_win, *win1 = b->d_win + gstride * cg;
+        for (int l = 1; l <= 2 * o.n; ++l) {
+            LvlArgs a = level_args(b, o, cycle_weight);
+            a.level = l;
+            a.group0 = c0;
+            a.cur = (l & 1) ? win1 : win0;
+            a.nxt = (l & 1) ? win0 : win1;
+            a.cur_gstride = a.nxt_gstride = gstride;
+            const int nm = o.hp->levels[l].w;
+            a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
+            a.out = d_out;
+            HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+        }
+    }
+    return COS_OK;
 }
 
 cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
@@ -449,29 +486,8 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
     if (st) return st;
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
     hipStream_t s = (hipStream_t)stream;
-    for (const OrderGroup &o : b->orders) {
-        HIP_TRY(tmark(b, COS_PHASE_PACK, s));
-        HIP_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
-        HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
-        const int64_t rs = (int64_t)b->nfs * o.n * 64;
-        const int64_t gstride = (int64_t)o.hp->max_rows * rs;
-        for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_fwd) {
-            const int cg = std::min(o.chunk_fwd, o.ngroups - c0);
-            double *win0 = b->d_win, *win1 = b->d_win + gstride * cg;
-            for (int l = 1; l <= 2 * o.n; ++l) {
-                LvlArgs a = level_args(b, o, cycle_weight);
-                a.level = l;
-                a.group0 = c0;
-                a.cur = (l & 1) ? win1 : win0;
-                a.nxt = (l & 1) ? win0 : win1;
-                a.cur_gstride = a.nxt_gstride = gstride;
-                const int nm = o.hp->levels[l].w;
-                a.mpb = masks_per_block(b->nfs, nm, cg, b->ncu);
-                a.out = d_out;
-                HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, s));
-            }
-        }
-    }
+    for (const OrderGroup &o : b->orders)
+        if ((st = forward_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out, s))) return st;
     HIP_TRY(tmark(b, -1, s));
     return COS_OK;
 }
@@ -481,9 +497,12 @@ static cos_status prepare_adjoint(cos_batch_t b) {
     int64_t fall = 0, gb = 0, sb = 0;
     for (OrderGroup &o : b->orders) {
         const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        // all forward levels and two adjoint windows
         const int64_t per_group = ((int64_t)o.hp->rows.size() + 2 * (int64_t)o.hp->max_rows) * rs;
         o.chunk_adj = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
         fall = std::max(fall, per_group * o.chunk_adj);
+        o.gb_off = gb;
+        o.sb_off = sb;
         gb += (int64_t)o.ngroups * b->nfs * o.n * o.n * 64;
         sb += (int64_t)o.ngroups * b->nfs * 64;
     }
@@ -502,6 +521,62 @@ static cos_status prepare_adjoint(cos_batch_t b) {
     return COS_OK;
 }
 
+// forward (every level kept) and reverse levels of one order
+static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double *d_G, const int64_t *d_Goff,
+                                const double *d_stub, double cycle_weight, const double *d_out_bar,
+                                double *d_out, double *d_G_bar, double *d_stub_bar, hipStream_t s) {
+    const PackArgs pa = pack_args(b, o, d_G, d_Goff, d_stub);
+    HIP_TRY(tmark(b, COS_PHASE_PACK, s));
+    HIP_TRY(launch_pack(pa, s));
+    double *GbT = b->d_GbT + o.gb_off, *sbT = b->d_sbT + o.sb_off;
+    const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.n * o.n * 64, nsb = (int64_t)o.ngroups * b->nfs * 64;
+    HIP_TRY(launch_zero(GbT, ngb, s));
+    HIP_TRY(launch_zero(sbT, nsb, s));
+    const int64_t rs = (int64_t)b->nfs * o.n * 64;
+    const int64_t total_rows = (int64_t)o.hp->rows.size();
+    const int64_t fstride = total_rows * rs, bstride = (int64_t)o.hp->max_rows * rs;
+    for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_adj) {
+        const int cg = std::min(o.chunk_adj, o.ngroups - c0);
+        double *Fall = b->d_Fall;
+        double *B0 = Fall + fstride * cg, *B1 = B0 + bstride * cg;
+        HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
+        for (int l = 1; l <= 2 * o.n; ++l) {   // forward, every level kept
+            LvlArgs a = level_args(b, o, cycle_weight);
+            a.level = l;
+            a.group0 = c0;
+            a.cur = a.nxt = Fall;
+            a.cur_gstride = a.nxt_gstride = fstride;
+            a.cur_row0 = o.hp->levels[l].x;
+            a.nxt_row0 = o.hp->levels[std::min(l + 1, 2 * o.n + 1)].x;
+            const int nm = o.hp->levels[l].w;
+            a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
+            a.out = d_out;
+            HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+        }
+        HIP_TRY(tmark(b, COS_PHASE_REVERSE, s));
+        for (int l = 2 * o.n; l >= 1; --l) {   // reverse
+            LvlArgs a = level_args(b, o, cycle_weight);
+            a.level = l;
+            a.group0 = c0;
+            a.cur = (l & 1) ? B0 : B1;         // adjoints of level + 1
+            a.nxt = (l & 1) ? B1 : B0;         // adjoints of level
+            a.cur_gstride = a.nxt_gstride = bstride;
+            a.F = Fall;
+            a.F_gstride = fstride;
+            a.F_row0 = o.hp->levels[l].x;
+            const int nm = o.hp->levels[l].w;
+            a.mpb = adj_masks(o.shape, nm, cg, b->ncu);
+            a.out_bar = d_out_bar;
+            a.Gbar_T = GbT;
+            a.sbar_T = sbT;
+            HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
+        }
+    }
+    HIP_TRY(tmark(b, COS_PHASE_UNPACK, s));
+    HIP_TRY(launch_unpack(pa, GbT, sbT, d_G_bar, (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr, s));
+    return COS_OK;
+}
+
 cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
                                      const double *d_stub, double cycle_weight,
                                      const double *d_out_bar, double *d_out, double *d_G_bar,
@@ -512,62 +587,106 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
     if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
     if ((st = prepare_adjoint(b))) return st;
     hipStream_t s = (hipStream_t)stream;
-    int64_t gb_off = 0, sb_off = 0;
-    for (const OrderGroup &o : b->orders) {
-        const PackArgs pa = pack_args(b, o, d_G, d_Goff, d_stub);
-        HIP_TRY(tmark(b, COS_PHASE_PACK, s));
-        HIP_TRY(launch_pack(pa, s));
-        double *GbT = b->d_GbT + gb_off, *sbT = b->d_sbT + sb_off;
-        const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.n * o.n * 64, nsb = (int64_t)o.ngroups * b->nfs * 64;
-        HIP_TRY(launch_zero(GbT, ngb, s));
-        HIP_TRY(launch_zero(sbT, nsb, s));
-        const int64_t rs = (int64_t)b->nfs * o.n * 64;
-        const int64_t total_rows = (int64_t)o.hp->rows.size();
-        const int64_t fstride = total_rows * rs, bstride = (int64_t)o.hp->max_rows * rs;
-        for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_adj) {
-            const int cg = std::min(o.chunk_adj, o.ngroups - c0);
-            double *Fall = b->d_Fall;
-            double *B0 = Fall + fstride * cg, *B1 = B0 + bstride * cg;
-            HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
-            for (int l = 1; l <= 2 * o.n; ++l) {   // forward, every level kept
-                LvlArgs a = level_args(b, o, cycle_weight);
-                a.level = l;
-                a.group0 = c0;
-                a.cur = a.nxt = Fall;
-                a.cur_gstride = a.nxt_gstride = fstride;
-                a.cur_row0 = o.hp->levels[l].x;
-                a.nxt_row0 = o.hp->levels[std::min(l + 1, 2 * o.n + 1)].x;
-                const int nm = o.hp->levels[l].w;
-                a.mpb = masks_per_block(b->nfs, nm, cg, b->ncu);
-                a.out = d_out;
-                HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, s));
-            }
-            HIP_TRY(tmark(b, COS_PHASE_REVERSE, s));
-            for (int l = 2 * o.n; l >= 1; --l) {   // reverse
-                LvlArgs a = level_args(b, o, cycle_weight);
-                a.level = l;
-                a.group0 = c0;
-                a.cur = (l & 1) ? B0 : B1;         // adjoints of level + 1
-                a.nxt = (l & 1) ? B1 : B0;         // adjoints of level
-                a.cur_gstride = a.nxt_gstride = bstride;
-                a.F = Fall;
-                a.F_gstride = fstride;
-                a.F_row0 = o.hp->levels[l].x;
-                const int nm = o.hp->levels[l].w;
-                a.mpb = adj_masks_per_wave(nm, cg, b->ncu);
-                a.out_bar = d_out_bar;
-                a.Gbar_T = GbT;
-                a.sbar_T = sbT;
-                HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, s));
-            }
-        }
-        HIP_TRY(tmark(b, COS_PHASE_UNPACK, s));
-        HIP_TRY(launch_unpack(pa, GbT, sbT, d_G_bar, (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr, s));
-        gb_off += ngb;
-        sb_off += nsb;
-    }
+    for (const OrderGroup &o : b->orders)
+        if ((st = adjoint_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar, d_stub_bar, s)))
+            return st;
     HIP_TRY(tmark(b, -1, s));
     return COS_OK;
+}
+
+// device time of fn() on stream s: one warm-up, then the best of `reps`
+static cos_status time_best(hipStream_t s, int reps, const std::function<cos_status()> &fn, float *best) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(COS_EDEVICE, "hipEventCreate failed");
+    }
+    cos_status st = fn();
+    *best = 1e30f;
+    for (int r = 0; r < reps && st == COS_OK; ++r) {
+        float t = 0.0f;
+        if (hipEventRecord(e0, s) != hipSuccess) { st = fail(COS_EDEVICE, "hipEventRecord failed"); break; }
+        if ((st = fn())) break;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
+            st = fail(COS_EDEVICE, "timing events failed");
+            break;
+        }
+        *best = std::min(*best, t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
+cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d_Goff, const double *d_stub,
+                              double cycle_weight, const double *d_out_bar, double *d_out, double *d_G_bar,
+                              double *d_stub_bar, void *stream) {
+    cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
+    if (st) return st;
+    if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
+    if (d_out_bar) {
+        if (!d_G_bar) return fail(COS_EINVAL, "d_G_bar is required to tune the reverse sweep");
+        if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
+        if ((st = prepare_adjoint(b))) return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool was_timing = b->timing;
+    b->timing = false;
+    static const int kWaves[] = {4, 8};
+    static const int kCaps[] = {1, 2, 4, 8, 16};
+    for (OrderGroup &o : b->orders) {
+        // forward: waves per workgroup x masks per wavefront
+        LaunchShape best = o.shape;
+        float tbest = 1e30f;
+        for (int wv : kWaves)
+            for (int cap : kCaps) {
+                o.shape.fwd_wpb = wv;
+                o.shape.fwd_cap = cap;
+                float t;
+                st = time_best(s, 3, [&] { return forward_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out, s); }, &t);
+                if (st) break;
+                if (t < tbest) { tbest = t; best = o.shape; }
+            }
+        o.shape = best;
+        if (st) break;
+        if (!d_out_bar) continue;
+        // reverse: masks per wavefront (the forward part is the same for every candidate)
+        tbest = 1e30f;
+        for (int cap : kCaps) {
+            o.shape.adj_cap = cap;
+            float t;
+            st = time_best(s, 3, [&] {
+                return adjoint_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar, d_stub_bar, s);
+            }, &t);
+            if (st) break;
+            if (t < tbest) { tbest = t; best.adj_cap = cap; }
+        }
+        o.shape = best;
+        if (st) break;
+    }
+    b->timing = was_timing;
+    if (st) return st;
+    // leave the outputs as a call with the chosen shapes writes them
+    if (d_out_bar) return cos_connected_sum_adjoint(b, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar,
+                                                    d_stub_bar, stream);
+    return cos_connected_sum_batched(b, d_G, d_Goff, d_stub, cycle_weight, d_out, stream);
+}
+
+cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves, int32_t *fwd_masks_cap,
+                                  int32_t *adj_masks_cap) {
+    if (!b || !fwd_waves || !fwd_masks_cap || !adj_masks_cap) return fail(COS_EINVAL, "null argument");
+    for (const OrderGroup &o : b->orders)
+        if (o.n == n) {
+            *fwd_waves = o.shape.fwd_wpb;
+            int cap = o.shape.fwd_cap ? o.shape.fwd_cap : (b->nfs <= 1 ? 8 : kMultiMasks);
+            if (b->nfs > 1) cap = std::min(cap, kMultiMasks);
+            *fwd_masks_cap = cap;
+            *adj_masks_cap = o.shape.adj_cap;
+            return COS_OK;
+        }
+    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
 }
 
 cos_status cos_batch_timing_enable(cos_batch_t b, int32_t enable) {

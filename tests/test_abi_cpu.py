@@ -73,6 +73,9 @@ def test_argument_validation_without_device(B):
     assert lib.cos_connected_sum_batched(None, None, None, None, -1.0, None, None) == -1
     assert lib.cos_build_g0(1, 1, 1, 1, 1, 0, 1.0, 1.0, 1, G.ctypes.data, G.ctypes.data, 1, 1, None, None) == -2
     assert lib.cos_chain_mu_shift(0, None, 1, None, None, None, None, 1, 1.0, None, None, None) == -1
+    assert lib.cos_batch_autotune(None, None, None, None, -1.0, None, None, None, None, None) == -1
+    i1, i2, i3 = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert lib.cos_batch_launch_shape(None, 10, ctypes.byref(i1), ctypes.byref(i2), ctypes.byref(i3)) == -1
     assert lib.cos_batch_timing_enable(None, 1) == -1
     ms = (ctypes.c_double * 4)()
     assert lib.cos_batch_timing_read(None, ms, None) == -1

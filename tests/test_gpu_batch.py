@@ -144,3 +144,64 @@ def test_phase_timing():
     assert calls2 == 0 and sum(ms2.values()) == 0.0
     b.timing(False)
     b.close()
+
+
+def test_autotune_keeps_results():
+    """The autotuner picks a launch shape per order; S is bitwise the same under
+    every shape, gradients agree to rounding (their accumulation order varies)."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("autotune, orders 4, 7, 9 with 3 flavours and shifts")
+    rng = np.random.default_rng(21)
+    orders = [9, 4, 7, 9, 4, 7, 9]
+    mats = [rng.normal(size=(3, n, n)) * 0.5 for n in orders]
+    sts = rng.normal(size=(len(orders), 3)) * 0.2
+    flat, off, n = pack(mats)
+    G, Goff, st = _dev(flat), _dev(off), _dev(sts)
+    b = B.Batch(n, 3, 1, stubs=True)
+    S0 = torch.empty(len(orders), dtype=torch.float64, device="cuda:0")
+    ob = _dev(rng.normal(size=len(orders)))
+    Gb0, sb0 = torch.empty_like(G), torch.empty_like(st)
+    b.adjoint(G, Goff, st, -1.0, ob, S0, Gb0, sb0)
+    S1 = torch.full_like(S0, float("nan"))
+    b.autotune(G, Goff, st, -1.0, S1, ob, torch.empty_like(G), torch.empty_like(st))
+    shapes = {k: b.launch_shape(k) for k in (4, 7, 9)}
+    for k, sh in shapes.items():
+        assert sh["fwd_waves"] in (4, 8) and sh["fwd_masks"] in (1, 2, 4, 8, 16) and sh["adj_masks"] in (1, 2, 4, 8, 16), sh
+    with pytest.raises(B.CosError):
+        b.launch_shape(5)
+    S2 = torch.full_like(S0, float("nan"))
+    b.forward(G, Goff, st, -1.0, S2)
+    Gb2, sb2 = torch.empty_like(G), torch.empty_like(st)
+    S3 = torch.full_like(S0, float("nan"))
+    b.adjoint(G, Goff, st, -1.0, ob, S3, Gb2, sb2)
+    torch.cuda.synchronize()
+    assert torch.equal(S0, S1) and torch.equal(S0, S2) and torch.equal(S0, S3)
+    assert torch.allclose(Gb2, Gb0, rtol=1e-12, atol=1e-14 * float(Gb0.abs().max()))
+    assert torch.allclose(sb2, sb0, rtol=1e-12, atol=1e-14 * float(sb0.abs().max()))
+    b.close()
+
+
+def test_many_flavours_fit_lds():
+    """16 flavours at n = 10: the forward's per-mask close sums of every flavour
+    sit in LDS beside G; the launch shape must shrink to fit.  Equal matrices
+    in every flavour reproduce the uniform variant."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("16 flavours at n=10 (flavour variant) vs uniform")
+    rng = np.random.default_rng(31)
+    M = rng.normal(size=(10, 10)) * 0.4
+    bf = B.Batch([10], 16, 1)
+    bu = B.Batch([10], 16, 0)
+    Sf = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda:0")
+    Su = torch.full_like(Sf, float("nan"))
+    bf.forward(_dev(np.tile(M, (16, 1, 1)).reshape(-1)), None, None, -1.0, Sf)
+    bu.forward(_dev(M.reshape(-1)), None, None, -1.0, Su)
+    Sa = torch.full_like(Sf, float("nan"))   # the same sum over absolute values
+    bu.forward(_dev(np.abs(M).reshape(-1)), None, None, 1.0, Sa)
+    torch.cuda.synchronize()
+    sf, su, sa = float(Sf[0]), float(Su[0]), float(Sa[0])
+    eps = np.finfo(np.float64).eps
+    assert np.isfinite(sf) and abs(sf - su) <= 2 * 8 * 10 * 12 * eps * sa, (sf, su, sa)
+    bf.close()
+    bu.close()
