@@ -17,7 +17,7 @@ namespace libcos {
 // current vertex, l the cycle's flavour.  Level = sum_k m_k (the number of
 // visited points, the layer index of Alg. 1-3).  States are grouped in rows
 // (m, u); a row holds one dense slot per vertex v (slots outside the row's
-// current set are never read).
+// current set are never read).  Buffers hold one plane of rows per flavour.
 //
 // Which rows and currents exist (reachable from the start (e_0, 0, 0)):
 //   row (m, 0) for every m with m_0 >= 1 (the first cycle is still open);
@@ -87,9 +87,10 @@ struct LvlArgs {
     const double *cur;        // forward: states of `level`; reverse: adjoints of level + 1
     double *nxt;              // forward: states of level + 1; reverse: adjoints of `level`
     int64_t cur_gstride, nxt_gstride;   // doubles per group
-    int32_t cur_row0, nxt_row0;         // first row of the level inside its buffer
+    int64_t cur_frows, nxt_frows;       // rows per flavour plane ([flavour][row][v][lane])
+    int32_t cur_row0, nxt_row0;         // first row of the level inside its plane
     const double *F;          // reverse: forward states of all levels
-    int64_t F_gstride;
+    int64_t F_gstride, F_frows;
     int32_t F_row0;
     int32_t level, group0, nfs, stubs, mpb;
     double W;                 // factor of one closed cycle: w * nflav (uniform) or w

@@ -132,11 +132,11 @@ __global__ void pack_kernel(const PackArgs A) {
 // ---------------------------------------------------------------------------
 template <int N>
 __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
-                                        double *__restrict__ nxt, uint32_t lane8, int nfs, int lam, int u, int r,
-                                        bool start, double sgx, double &cp, double &dext) {
+                                        double *__restrict__ nxt, uint32_t lane8, int64_t cpl, int64_t npl, int lam,
+                                        int u, int r, bool start, double sgx, double &cp, double &dext) {
     const uint32_t ones = M.ones, twos = M.twos;
     const uint32_t cm = current_set(u, ones, twos);
-    const double *__restrict__ src = cur + ((int64_t)r * nfs + lam) * N * 64;
+    const double *__restrict__ src = cur + lam * cpl + (int64_t)r * N * 64;
     // G comes from LDS for every row: an opaque base keeps the N^2 reads inside
     // the row instead of hoisted into N^2 registers for the whole loop
     asm volatile("" : "+v"(gaddr));
@@ -175,16 +175,16 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
         }
         const uint32_t ctw = first ? twos : (twos | bit);
         const int crow = M.crb[w] + head_slot(u, ctw);
-        lane_st(nxt + ((int64_t)crow * nfs + lam) * N * 64 + w * 64, lane8, val);
+        lane_st(nxt + lam * npl + (int64_t)crow * N * 64 + w * 64, lane8, val);
     }
 }
 
 template <int N>
-__device__ __forceinline__ void fwd_close(const MaskRec<N> &M, double *__restrict__ nxt, uint32_t lane8, int nfs,
-                                          int lam, double t, double dext) {
+__device__ __forceinline__ void fwd_close(const MaskRec<N> &M, double *__restrict__ nxt, uint32_t lane8,
+                                          int64_t npl, int lam, double t, double dext) {
     const int h = __builtin_ctz(M.ones);
     const int crow = close_row_base<N>(M, h) + head_slot(h, M.twos | (1u << h));
-    lane_st(nxt + ((int64_t)crow * nfs + lam) * N * 64 + h * 64, lane8, t + (h == 0 ? dext : 0.0));
+    lane_st(nxt + lam * npl + (int64_t)crow * N * 64 + h * 64, lane8, t + (h == 0 ? dext : 0.0));
 }
 
 // with several flavours (kMultiMasks masks per wavefront at most) the close
@@ -201,10 +201,11 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
     const int mb1 = min(mb0 + A.mpb, L.w);     // may be empty: the wave still joins the barriers
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
-    const int64_t RS = (int64_t)nfs * N * 64;
-    // wave-uniform bases; the lane's word is added at each access
-    const double *__restrict__ cur = A.cur + gl * A.cur_gstride + (int64_t)A.cur_row0 * RS;
-    double *__restrict__ nxt = A.nxt + gl * A.nxt_gstride + (int64_t)A.nxt_row0 * RS;
+    // wave-uniform bases; the lane's word is added at each access.  States are
+    // stored by flavour plane: [flavour][row][v][lane], planes of *_frows rows
+    const double *__restrict__ cur = A.cur + gl * A.cur_gstride + (int64_t)A.cur_row0 * N * 64;
+    double *__restrict__ nxt = A.nxt + gl * A.nxt_gstride + (int64_t)A.nxt_row0 * N * 64;
+    const int64_t cpl = A.cur_frows * N * 64, npl = A.nxt_frows * N * 64;
     const uint32_t lane8 = (uint32_t)lane * 8u;
     const uint32_t gaddr = lds_addr(Gs_all) + lane * 8u;
     const int cfg = A.lane_cfg[g * 64 + lane];
@@ -232,7 +233,7 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
                 int u = 0, slot = 0;
                 double cp = 0.0, dext = 0.0;
                 while (true) {
-                    fwd_row<N>(M, gaddr, cur, nxt, lane8, nfs, lam, u, M.rb + slot, start, sgx, cp, dext);
+                    fwd_row<N>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, M.rb + slot, start, sgx, cp, dext);
                     if (!hs) break;
                     u = __builtin_ctz(hs);
                     hs &= hs - 1u;
@@ -242,13 +243,13 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
                     cpk[k] += cp;
                     // m_0 = 1 (so h = 0): this flavour's extension into the slot
                     // the next cycle opens on; the close adds to it at the end
-                    if (!last && (ones & 1u)) fwd_close<N>(M, nxt, lane8, nfs, lam, 0.0, dext);
+                    if (!last && (ones & 1u)) fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
                 } else {
                     const double t = A.W * cp;
                     if (last) {
                         if (cfg >= 0 && A.out) A.out[cfg] = t;
                     } else if (ones) {
-                        fwd_close<N>(M, nxt, lane8, nfs, 0, t, dext);
+                        fwd_close<N>(M, nxt, lane8, npl, 0, t, dext);
                     }
                 }
             }
@@ -267,11 +268,11 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
             } else if (M.ones) {
                 const int h = __builtin_ctz(M.ones);
                 const int crow = close_row_base<N>(M, h) + head_slot(h, M.twos | (1u << h));
-                double *dst = nxt + (int64_t)crow * nfs * N * 64 + h * 64;
+                double *dst = nxt + (int64_t)crow * N * 64 + h * 64;
                 for (int lam = 0; lam < nfs; ++lam) {
                     // h = 0: the slot holds this wave's own extension value (written above)
-                    const double x = h == 0 ? lane_ld(dst + lam * N * 64, lane8) : 0.0;
-                    lane_st(dst + lam * N * 64, lane8, t + x);
+                    const double x = h == 0 ? lane_ld(dst + lam * npl, lane8) : 0.0;
+                    lane_st(dst + lam * npl, lane8, t + x);
                 }
             }
         }
@@ -295,12 +296,13 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
 template <int N>
 __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
                                         const double *__restrict__ F, const double *__restrict__ Bn,
-                                        double *__restrict__ Bc, uint32_t lane8, int nfs, int lam, int u, int r,
-                                        bool start, double tb, double sgx, double sc, double &sacc) {
+                                        double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
+                                        int64_t npl, int lam, int u, int r, bool start, double tb, double sgx,
+                                        double sc, double &sacc) {
     const uint32_t ones = M.ones, twos = M.twos;
     const uint32_t cm = current_set(u, ones, twos);
     const int v0 = cm ? __builtin_ctz(cm) : 0;   // every reachable row has a current; guard anyway
-    const double *__restrict__ src = F + ((int64_t)r * nfs + lam) * N * 64;
+    const double *__restrict__ src = F + lam * fpl + (int64_t)r * N * 64;
     // every load is issued (the unused ones re-read a slot this row needs
     // anyway) and the values are selected: straight-line code, no per-slot
     // control flow joining whole arrays
@@ -316,7 +318,7 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
         const uint32_t bit = 1u << w;
         const bool open = !(twos & bit), first = !(ones & bit);
         const int crow = open ? M.crb[w] + head_slot(u, first ? twos : (twos | bit)) : 0;
-        const double bc = lane_ld(Bn + (open ? ((int64_t)crow * nfs + lam) * N * 64 + w * 64 : 0), lane8);
+        const double bc = lane_ld(Bn + (open ? lam * cpl + (int64_t)crow * N * 64 + w * 64 : 0), lane8);
         a[w] = open ? (first ? 2.0 * bc : bc) : 0.0;
         const bool shift = open && !first && (cm & bit);
         sacc = shift ? __builtin_fma(-sc * f[w], bc, sacc) : sacc;
@@ -329,7 +331,7 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
     asm volatile("" : "+v"(gbaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
     lds_double *Gb = (lds_double *)(uintptr_t)gbaddr;
-    double *__restrict__ dst = Bc + ((int64_t)r * nfs + lam) * N * 64;
+    double *__restrict__ dst = Bc + lam * npl + (int64_t)r * N * 64;
 #pragma unroll
     for (int v = 0; v < N; ++v) {
         const uint32_t bit = 1u << v;
@@ -364,9 +366,9 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     const int mb1 = min(mb0 + A.mpb, L.w);    // may be empty: the wave still joins the barriers
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
-    const int64_t RS = (int64_t)nfs * N * 64;
-    // wave-uniform bases; the lane's word is added at each access
-    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * RS;
+    // wave-uniform bases; the lane's word is added at each access; flavour planes
+    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * N * 64;
+    const int64_t fpl = A.F_frows * N * 64, cpl = A.cur_frows * N * 64, npl = A.nxt_frows * N * 64;
     const double *__restrict__ Bn = A.cur + gl * A.cur_gstride;   // level + 1
     double *__restrict__ Bc = A.nxt + gl * A.nxt_gstride;         // level
     const uint32_t lane8 = (uint32_t)lane * 8u;
@@ -394,14 +396,15 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             } else if (ones) {
                 const int h = __builtin_ctz(ones);
                 const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
-                for (int k = 0; k < nfs; ++k) tb += lane_ld(Bn + ((int64_t)crow * nfs + k) * N * 64 + h * 64, lane8);
+                for (int k = 0; k < nfs; ++k) tb += lane_ld(Bn + k * cpl + (int64_t)crow * N * 64 + h * 64, lane8);
             }
             tb *= A.W;
             const double sc = (M.code == 1 ? 2.0 : 1.0);
             uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
             int u = 0, slot = 0;
             while (true) {
-                adj_row<N>(M, gaddr, gbaddr, F, Bn, Bc, lane8, nfs, lam, u, M.rb + slot, start, tb, sg * sc, sc, sacc);
+                adj_row<N>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start, tb, sg * sc,
+                           sc, sacc);
                 if (!hs) break;
                 u = __builtin_ctz(hs);
                 hs &= hs - 1u;

@@ -470,6 +470,7 @@ static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double
             a.cur = (l & 1) ? win1 : win0;
             a.nxt = (l & 1) ? win0 : win1;
             a.cur_gstride = a.nxt_gstride = gstride;
+            a.cur_frows = a.nxt_frows = o.hp->max_rows;
             const int nm = o.hp->levels[l].w;
             a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
             a.out = d_out;
@@ -546,6 +547,7 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
             a.group0 = c0;
             a.cur = a.nxt = Fall;
             a.cur_gstride = a.nxt_gstride = fstride;
+            a.cur_frows = a.nxt_frows = total_rows;
             a.cur_row0 = o.hp->levels[l].x;
             a.nxt_row0 = o.hp->levels[std::min(l + 1, 2 * o.n + 1)].x;
             const int nm = o.hp->levels[l].w;
@@ -561,8 +563,10 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
             a.cur = (l & 1) ? B0 : B1;         // adjoints of level + 1
             a.nxt = (l & 1) ? B1 : B0;         // adjoints of level
             a.cur_gstride = a.nxt_gstride = bstride;
+            a.cur_frows = a.nxt_frows = o.hp->max_rows;
             a.F = Fall;
             a.F_gstride = fstride;
+            a.F_frows = total_rows;
             a.F_row0 = o.hp->levels[l].x;
             const int nm = o.hp->levels[l].w;
             a.mpb = adj_masks(o.shape, nm, cg, b->ncu);
