@@ -147,14 +147,14 @@ def main():
     def evpair():
         return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
-    def step(e=None):
-        if e: e["g0"][0].record(stream)
-        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
-        if e: e["g0"][1].record(stream); e["adj"][0].record(stream)
-        batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
-        if e: e["adj"][1].record(stream); e["chain"][0].record(stream)
-        B.chain_mu_shift(nconf, geo.n, 1, geo.Goff, Gb, dG, sb, 1, w.U, mub, alb, stream)
-        if e: e["chain"][1].record(stream)
+    def step(e=None, st=stream):
+        if e: e["g0"][0].record(st)
+        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, st)
+        if e: e["g0"][1].record(st); e["adj"][0].record(st)
+        batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, st)
+        if e: e["adj"][1].record(st); e["chain"][0].record(st)
+        B.chain_mu_shift(nconf, geo.n, 1, geo.Goff, Gb, dG, sb, 1, w.U, mub, alb, st)
+        if e: e["chain"][1].record(st)
 
     for _ in range(args.warmup):
         step()
@@ -174,6 +174,26 @@ def main():
     acc = {k: sum(e[k][0].elapsed_time(e[k][1]) for e in evs) for k in ("g0", "adj", "chain")}
     ms_step = 1e3 * wall / args.steps
     value = nconf / (wall / args.steps)
+
+    # the same step replayed from a HIP graph (captured once; no host launches)
+    graph = torch.cuda.CUDAGraph()
+    cs = torch.cuda.Stream()
+    cs.wait_stream(stream)
+    with torch.cuda.stream(cs):
+        step(st=cs)
+    stream.wait_stream(cs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=cs):
+        step(st=cs)
+    graph.replay()
+    torch.cuda.synchronize()
+    ge0, ge1 = evpair()
+    ge0.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    ge1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = ge0.elapsed_time(ge1) / args.steps
 
     # batched forward alone (G0 + forward) and the plain one-launch-per-config form
     def fwd_batched():
@@ -267,6 +287,7 @@ def main():
         "breakdown_ms": {"g0": acc["g0"] / args.steps, "adjoint_incl_forward": acc["adj"] / args.steps,
                          "chain": acc["chain"] / args.steps,
                          "adjoint_phases": {k: v / args.steps for k, v in phases.items()}},
+        "graph_replay": {"ms_per_step": graph_ms, "configs_per_s": nconf / (graph_ms * 1e-3)},
         "forward_batched_configs_per_s": nconf / (fwd_ms * 1e-3),
         "forward_kernel_ms": fwd_kernel_ms,
         "forward_plain_configs_per_s": nconf / (plain_ms * 1e-3),

@@ -72,9 +72,10 @@ def workload_params(draw):
     return nmat, w.nflav, w.variant, mu, alpha, stubs
 
 
-def gpu_workload(draw, adjoint=False):
+def gpu_workload(draw, adjoint=False, tune=False):
     """Propagators (G0 kernel) and connected sums (forward kernel) of a drawn
-    workload, all on the GPU; returns host copies."""
+    workload, all on the GPU; returns host copies.  tune=True first runs the
+    autotuner (the launch shapes bench.py times)."""
     import torch
     from paper_2507_12349_amd import _binding as B
     from paper_2507_12349_amd.autograd import Geometry
@@ -86,6 +87,11 @@ def gpu_workload(draw, adjoint=False):
     b = B.Batch(draw.n, nflav, variant, stubs=stubs is not None)
     st = None if stubs is None else torch.as_tensor(stubs, device=geo.device)
     out = torch.full((geo.nconf,), float("nan"), dtype=torch.float64, device=geo.device)
+    if tune:
+        ob = torch.ones(geo.nconf, dtype=torch.float64, device=geo.device)
+        b.autotune(G, geo.Goff, st, -1.0, out, ob if adjoint else None, torch.empty_like(G) if adjoint else None,
+                   None if st is None else torch.empty_like(st))
+        out.fill_(float("nan"))
     b.forward(G, geo.Goff, st, -1.0, out)
     res = dict(G=G.cpu().numpy(), dG=dG.cpu().numpy(), S=None, Goff=geo.Goff_host, nmat=nmat, nflav=nflav,
                variant=variant, mu=mu, alpha=alpha, stubs=stubs)
@@ -102,6 +108,7 @@ def gpu_workload(draw, adjoint=False):
         B.chain_mu_shift(geo.nconf, geo.n, nmat, geo.Goff, Gb, dG, sb, 1 if st is None else st.shape[1],
                          draw.workload.U, mub, alb)
         torch.cuda.synchronize()
+        res["shape"] = b.launch_shape(int(draw.n[0]))
         res.update(S2=out2.cpu().numpy(), Gb=Gb.cpu().numpy(), sb=None if sb is None else sb.cpu().numpy(),
                    mub=mub.cpu().numpy().reshape(geo.nconf, nmat), alb=alb.cpu().numpy().reshape(geo.nconf, nmat))
     b.close()

@@ -41,15 +41,17 @@ def test_random_adjoint(oracle_mod, nf, variant, stubs):
 
 
 def test_adjoint_workload(oracle_mod):
-    """Adjoint workload (2048 configs, n = 10, SU(4), shifts at delta = 0):
+    """Adjoint workload (2048 configs, n = 10, SU(4), shifts at delta = 0) in
+    the launch shapes bench.py times (autotuned):
     full batch forward + reverse on the GPU; sampled configurations against
     the oracle's reverse sweep, the Euler identity, and finite differences of
     the oracle in mu and in one flavour's shift."""
     from oracle import g0
-    announce("adjoint workload 2048 x n=10")
+    announce("adjoint workload 2048 x n=10, autotuned launch shapes")
     d = draw("adjoint")
     w = d.workload
-    res = gpu_workload(d, adjoint=True)
+    res = gpu_workload(d, adjoint=True, tune=True)
+    announce("launch shape %s" % res["shape"])
     assert np.array_equal(res["S"], res["S2"])
     assert np.all(np.isfinite(res["Gb"]))
     rng = np.random.default_rng(55)

@@ -93,6 +93,47 @@ def test_graph_replay_with_new_inputs():
     b.close()
 
 
+def test_graph_replay_adjoint_uneven():
+    """The adjoint of an uneven batch (orders 5, 7, 9; three flavours with
+    shifts) captured once and replayed with new inputs: S equals an eager call
+    bit for bit, the gradients to rounding (their accumulation order varies)."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("graph capture / replay of the adjoint, uneven orders")
+    rng = np.random.default_rng(9)
+    orders = [9, 5, 7, 9, 5, 7, 7]
+    mats = [rng.normal(size=(3, k, k)) * 0.5 for k in orders]
+    flat, off, n = pack(mats)
+    b = B.Batch(n, 3, 1, stubs=True)
+    G, Goff = _dev(flat), _dev(off)
+    st = _dev(rng.normal(size=(len(orders), 3)) * 0.2)
+    ob = _dev(rng.normal(size=len(orders)))
+    S, Gb, sb = torch.zeros(len(orders), dtype=torch.float64, device="cuda:0"), torch.zeros_like(G), torch.zeros_like(st)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.adjoint(G, Goff, st, -1.0, ob, S, Gb, sb)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.adjoint(G, Goff, st, -1.0, ob, S, Gb, sb)
+    rS, rGb, rsb = torch.zeros_like(S), torch.zeros_like(Gb), torch.zeros_like(sb)
+    for k in range(3):
+        G.copy_(_dev(np.concatenate([(rng.normal(size=m.shape) * 0.5).reshape(-1) for m in mats])))
+        st.copy_(_dev(rng.normal(size=(len(orders), 3)) * 0.2))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        gS, gGb, gsb = S.clone(), Gb.clone(), sb.clone()
+        b.adjoint(G, Goff, st, -1.0, ob, rS, rGb, rsb)
+        torch.cuda.synchronize()
+        assert torch.equal(gS, rS), k
+        assert torch.allclose(gGb, rGb, rtol=1e-12, atol=1e-14 * float(rGb.abs().max())), k
+        assert torch.allclose(gsb, rsb, rtol=1e-12, atol=1e-14 * float(rsb.abs().max())), k
+    b.close()
+
+
 def test_autograd_function_matches_adjoint():
     import torch
     from paper_2507_12349_amd import _binding as B
