@@ -1,0 +1,66 @@
+"""Pins of the sublattice-summed oracle (bipartite lattices): the sum over
+label assignments (oracle) against an independent enumeration of labelled
+permutations, a closed form for label-factorised propagators, the label-swap
+symmetry, diagram counts, and the labelled state space."""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import sublattice as SL
+
+
+def _rand(rng, n, nmat):
+    return rng.normal(size=(nmat, 2 * n, 2 * n)) * 0.7
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+@pytest.mark.parametrize("nf,variant", [(2, 0), (3, 0), (2, 1)])
+def test_assignment_sum_equals_labelled_enumeration(oracle_mod, n, nf, variant):
+    rng = np.random.default_rng(100 * n + 10 * nf + variant)
+    A = _rand(rng, n, 1 if variant == 0 else nf)
+    A = A[0] if variant == 0 else A
+    got = SL.by_assignment(A, nf, variant)
+    ref = SL.brute_labeled(A, nf, variant)
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (got, ref)
+
+
+@pytest.mark.parametrize("n", [2, 4, 6])
+def test_label_factorised_closed_form(oracle_mod, n):
+    """A[(k,s),(j,t)] = x_s y_t G[k][j]: every vertex has two points, each with
+    one outgoing and one incoming edge, so an assignment scales the sum by
+    prod_k (x_{s_k} y_{s_k})^2 and the total is S(G) (sum_s (x_s y_s)^2)^n."""
+    rng = np.random.default_rng(7 + n)
+    G = rng.normal(size=(n, n)) * 0.6
+    x, y = rng.normal(size=2), rng.normal(size=2)
+    A = np.einsum("s,t,kj->ksjt", x, y, G).reshape(2 * n, 2 * n)
+    got = SL.by_assignment(A, 3, 0)
+    ref = oracle_mod.dp(G, 3, 0) * (np.sum((x * y) ** 2)) ** n
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)) * 4 ** n
+
+
+@pytest.mark.parametrize("n", [3, 5])
+def test_label_swap_symmetry(oracle_mod, n):
+    rng = np.random.default_rng(40 + n)
+    A = _rand(rng, n, 2)
+    perm = np.array([2 * k + 1 - s for k in range(n) for s in (0, 1)])
+    a = SL.by_assignment(A, 2, 1)
+    b = SL.by_assignment(A[:, perm][:, :, perm], 2, 1)
+    assert abs(a - b) <= 1e-12 * max(1.0, abs(a))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5])
+def test_counts(oracle_mod, n):
+    """All propagators 1: every assignment gives the counting sequence c_n(w N)."""
+    from oracle import counts
+    got = SL.by_assignment(np.ones((2 * n, 2 * n)), 1, 0, 1.0)
+    assert got == 2 ** n * counts.connected_counts(n, 1)[n]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 5, 6])
+def test_state_space(n):
+    c = SL.plan_counts(n)
+    assert c["masks"] == 3 * 4 ** (n - 1)
+    assert c["closes"] == c["states"]
+    # each state of level l < 2n extends to one child per (open vertex, admissible label)
+    assert c["ext"] > c["states"] or n == 1
