@@ -33,7 +33,8 @@
  * completion of the work queued on the stream).  "d_" arguments are device
  * pointers on the current HIP device, others are host pointers.  Matrices are
  * FP64, row-major: config c, matrix g (0 for COS_UNIFORM, the flavour
- * otherwise), entry [k][j] is at d_G[d_Goff[c] + (g*n_c + k)*n_c + j].
+ * otherwise), entry [k][j] is at d_G[d_Goff[c] + (g*n_c + k)*n_c + j]
+ * (with COS_F_SUBLATTICE the side is 2 n_c instead of n_c).
  * Shift weights: d_stub[c*nstub + g], nstub = 1 (COS_UNIFORM) or nflav.
  *
  * Errors.  Every function returns cos_status.  Arguments are validated before
@@ -63,9 +64,20 @@ typedef enum {
 
 #define COS_NMAX 12
 #define COS_FMAX 16
+#define COS_NMAX_SUBLATTICE 8
 
 enum { COS_UNIFORM = 0, COS_FLAVOUR = 1 };
-enum { COS_F_STUBS = 1 };
+/* COS_F_SUBLATTICE: bipartite lattices (Results, four-state interaction mask
+ * {0, (1,A), (1,B), 2}; Alg. 1/2; Methods, strategy (i): the sum over every
+ * sublattice assignment).  Every vertex k also carries a label s_k in {A, B}
+ * shared by its two points, and the sum runs over all 2^n labellings in one
+ * pass.  Matrices are then 2n x 2n per configuration and flavour, row-major,
+ * index 2k + s (s = 0 for A, 1 for B): entry [2k+s][2j+t] is the propagator
+ * from vertex k on sublattice s to vertex j on sublattice t.  Orders up to
+ * COS_NMAX_SUBLATTICE; forward sums only (the adjoint and the autotuner's
+ * reverse sweep return COS_EUNSUPPORTED); not combinable with COS_F_STUBS
+ * (shifts enter through the matrices' diagonals). */
+enum { COS_F_STUBS = 1, COS_F_SUBLATTICE = 2 };
 
 typedef struct cos_batch_s *cos_batch_t;
 
@@ -173,6 +185,11 @@ enum { COS_PHASE_PACK = 0, COS_PHASE_FORWARD = 1, COS_PHASE_REVERSE = 2, COS_PHA
        COS_NPHASES = 4 };
 cos_status cos_batch_timing_enable(cos_batch_t b, int32_t enable);
 cos_status cos_batch_timing_read(cos_batch_t b, double *ms, int32_t *ncalls);
+
+/* Plan counts of the sublattice-labelled state space for order n (1..8),
+ * per flavour: states, extension transitions, closes, masks, rows. */
+cos_status cos_plan_counts_sublattice(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
+                                      int64_t *masks, int64_t *rows);
 
 /* Diagnostics. */
 const char *cos_status_string(cos_status s);

@@ -16,14 +16,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcos.so")
 
 UNIFORM, FLAVOUR = 0, 1
-F_STUBS = 1
-NMAX, FMAX = 12, 16
+F_STUBS, F_SUBLATTICE = 1, 2
+NMAX, FMAX, NMAX_SUBLATTICE = 12, 16, 8
 
 EXPORTED = (
     "cos_batch_create", "cos_batch_destroy", "cos_connected_sum_batched",
     "cos_connected_sum_adjoint", "cos_connected_sum", "cos_build_g0", "cos_chain_mu_shift",
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
+    "cos_plan_counts_sublattice",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -48,6 +49,7 @@ def _load():
         "cos_build_g0": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p], i32),
         "cos_chain_mu_shift": ([i32, p, i32, p, p, p, p, i32, d, p, p, p], i32),
         "cos_plan_counts": ([i32, P64, P64, P64, P64, P64, P64], i32),
+        "cos_plan_counts_sublattice": ([i32, P64, P64, P64, P64, P64], i32),
         "cos_status_string": ([i32], ctypes.c_char_p),
         "cos_last_error": ([], ctypes.c_char_p),
         "cos_release": ([], i32),
@@ -103,6 +105,12 @@ def plan_counts(n: int) -> dict:
     return dict(zip(("states", "ext", "closes", "stub_edges", "masks", "rows"), [v.value for v in vals]))
 
 
+def plan_counts_sublattice(n: int) -> dict:
+    vals = [ctypes.c_int64() for _ in range(5)]
+    _check(lib.cos_plan_counts_sublattice(int(n), *[ctypes.byref(v) for v in vals]), "cos_plan_counts_sublattice")
+    return dict(zip(("states", "ext", "closes", "masks", "rows"), [v.value for v in vals]))
+
+
 def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=None, w: float = -1.0) -> float:
     """One configuration from host arrays (the GPU kernel does the work)."""
     G = np.ascontiguousarray(G, dtype=np.float64)
@@ -118,18 +126,20 @@ def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=N
 class Batch:
     """Plan for a batch of configurations with orders ``n`` (host sequence)."""
 
-    def __init__(self, n, nflav: int, variant: int = UNIFORM, stubs: bool = False):
+    def __init__(self, n, nflav: int, variant: int = UNIFORM, stubs: bool = False, sublattice: bool = False):
         n = np.ascontiguousarray(np.asarray(n, dtype=np.int32).reshape(-1))
         self.n = n
         self.nconf = int(n.size)
         self.nflav = int(nflav)
         self.variant = int(variant)
         self.stubs = bool(stubs)
+        self.sublattice = bool(sublattice)
         self.nmat = self.nflav if self.variant == FLAVOUR else 1
         self.nstub = self.nmat
         h = ctypes.c_void_p()
-        _check(lib.cos_batch_create(self.nconf, _ptr(n), self.nflav, self.variant,
-                                    F_STUBS if self.stubs else 0, ctypes.byref(h)), "cos_batch_create")
+        flags = (F_STUBS if self.stubs else 0) | (F_SUBLATTICE if self.sublattice else 0)
+        _check(lib.cos_batch_create(self.nconf, _ptr(n), self.nflav, self.variant, flags, ctypes.byref(h)),
+               "cos_batch_create")
         self._h = h
 
     def close(self):
@@ -145,7 +155,8 @@ class Batch:
 
     def goff(self):
         """Element offsets of each configuration's matrices (back-to-back layout)."""
-        sizes = self.nmat * self.n.astype(np.int64) ** 2
+        side = self.n.astype(np.int64) * (2 if self.sublattice else 1)
+        sizes = self.nmat * side ** 2
         off = np.zeros(self.nconf, dtype=np.int64)
         off[1:] = np.cumsum(sizes[:-1])
         return off, int(sizes.sum())

@@ -67,6 +67,43 @@ __host__ __device__ inline uint32_t current_set(int u, uint32_t ones, uint32_t t
     return c;
 }
 
+// ---------------------------------------------------------------------------
+// Sublattice-labelled state space (bipartite lattices; Results, four-state
+// interaction mask {0, (1,A), (1,B), 2}; Alg. 1/2).  Every vertex k carries a
+// label s_k in {A = 0, B = 1} shared by its two points; matrices are 2n x 2n,
+// index 2k + s.  Mask digit (base 4): 0 unvisited, 1 once on A, 2 once on B,
+// 3 twice (the label is forgotten).  ones / twos as above, subb = vertices
+// visited once on B.  A row is (m, u, s_u); a slot is (v, s_v), index 2v + s_v.
+//   rows of m: (0, s_0) only, when m_0 is once-visited (s_0 from the mask);
+//   otherwise (0, A), (0, B), then (h, A), (h, B) for each h >= 1 with m_h = 2;
+//   current slots of (m, u, s_u): for v in current_set(u, ...): (v, label from
+//   the mask) if v is once-visited, (u, s_u) if v = u, both labels otherwise.
+// Mask records (kSubRecInts ints): [0] code (base 4), [1] ones | (twos << 16),
+// [2] level-relative row of the mask's first row, [3] subb,
+// [4 + 2w + s] first row of the child mask reached by visiting (w, s) (-1 when
+// not allowed: w visited twice, or once with the other label).
+// ---------------------------------------------------------------------------
+constexpr int kSubNmax = 8;       // G of 64 lanes, (2n)^2 doubles each, must fit LDS
+constexpr int kSubRecInts = 24;
+static_assert(4 + 2 * kSubNmax <= kSubRecInts, "sublattice mask record too small");
+
+__host__ __device__ inline int sub_head_slot(int u, int su, uint32_t twos) {
+    if (u == 0) return (twos & 1u) ? su : 0;
+    return 2 + 2 * __builtin_popcount(twos & ((1u << u) - 1u) & ~1u) + su;
+}
+
+__host__ __device__ inline uint32_t sub_current(int n, int u, int su, uint32_t ones, uint32_t twos, uint32_t subb) {
+    const uint32_t cm = current_set(u, ones, twos);
+    uint32_t out = 0;
+    for (int v = 0; v < n; ++v) {
+        if (!((cm >> v) & 1u)) continue;
+        if ((ones >> v) & 1u) out |= 1u << (2 * v + ((subb >> v) & 1u));
+        else if (v == u) out |= 1u << (2 * v + su);
+        else out |= 3u << (2 * v);
+    }
+    return out;
+}
+
 // packing between the caller's layout and the per-lane layout of one order
 struct PackArgs {
     const double *G;          // caller matrices
@@ -104,6 +141,9 @@ hipError_t launch_pack(const PackArgs &a, hipStream_t s);
 hipError_t launch_unpack(const PackArgs &a, const double *GbT, const double *sbT, double *Gb, double *sb,
                          hipStream_t s);
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
+// sublattice forward level (cos_sub.hip): `a.plan` is a sublattice plan, rows
+// hold 2n slots, GT holds 2n x 2n matrices; wpb <= 16
+hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s);
 // nblocks = blocks of `a.mpb` masks; `wpb` wavefronts per workgroup (forward:
 // at most 8; the reverse kernel always runs adj_waves_per_block())
 hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s);

@@ -22,16 +22,9 @@
 //   close: t_m = W sum_{u,l} acc[u]; the next cycle opens at
 //   h = min{k : m_k = 1} with value t_m in every flavour, or S = t_m at the
 //   full mask.
-#include "cos_internal.hpp"
+#include "cos_device.hpp"
 
 namespace libcos {
-
-#define COS_RF(x) __builtin_amdgcn_readfirstlane(x)
-
-typedef __attribute__((address_space(3))) double lds_double;
-// read-only tables read at wave-uniform addresses: through the constant
-// address space they are fetched with scalar loads
-typedef const __attribute__((address_space(4))) int32_t cint32;
 
 // one mask of a level: its code bits, row base and child row bases
 template <int N>
@@ -55,11 +48,6 @@ __device__ __forceinline__ MaskRec<N> load_rec(const DevPlan &P, int gi) {
     return m;
 }
 
-__device__ __forceinline__ int4 load_level(const DevPlan &P, int l) {
-    const cint32 *p = (const cint32 *)(P.levels + l);
-    return make_int4(p[0], p[1], p[2], p[3]);
-}
-
 // child row base for the vertex h that opens the next cycle (h is wave-uniform;
 // a select chain keeps the record in scalar registers)
 template <int N>
@@ -68,27 +56,6 @@ __device__ __forceinline__ int close_row_base(const MaskRec<N> &M, int h) {
 #pragma unroll
     for (int w = 0; w < N; ++w) rb = (w == h) ? M.crb[w] : rb;
     return rb;
-}
-
-// LDS byte address of a __shared__ pointer
-__device__ __forceinline__ uint32_t lds_addr(double *p) {
-    return (uint32_t)(uintptr_t)(lds_double *)p;
-}
-
-// a lane's word of a 64-wide slot: wave-uniform base + the lane's byte offset
-// (scalar base registers, one 32-bit offset register per lane)
-// (the empty asm pins the base in scalar registers, so that it is not folded
-// into a per-lane 64-bit address)
-typedef __attribute__((address_space(1))) char global_char;
-__device__ __forceinline__ double lane_ld(const double *base, uint32_t lane8) {
-    const global_char *p = (const global_char *)base;
-    asm volatile("" : "+s"(p));
-    return *(const __attribute__((address_space(1))) double *)(p + lane8);
-}
-__device__ __forceinline__ void lane_st(double *base, uint32_t lane8, double x) {
-    global_char *p = (global_char *)base;
-    asm volatile("" : "+s"(p));
-    *(__attribute__((address_space(1))) double *)(p + lane8) = x;
 }
 
 // ---------------------------------------------------------------------------

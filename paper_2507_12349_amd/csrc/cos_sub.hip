@@ -1,0 +1,237 @@
+// Sublattice-summed forward levels (bipartite lattices): the connected sum over
+// every assignment of a sublattice label to each vertex, in one pass over the
+// labelled state space (Results, four-state interaction mask; Alg. 1/2).
+//
+// Same organisation as the unlabelled level kernels: one configuration per
+// lane, wave-uniform control flow from scalar mask records, one launch per
+// level.  A row (m, u, s_u) holds 2n slots (v, s_v); the 2n x 2n matrix of the
+// current flavour sits in LDS as [2n][2n][lane] ((2n)^2 x 512 B, 128 KB at
+// n = 8), shared by the 16 wavefronts of a workgroup.
+//
+// Rules per row (m, u, s_u), current slots f[(v, s_v)], acc = f . G:
+//   a once-unvisited w is reached on either label: child (m + (w, s)), slot
+//   (w, s) = 2 acc[(w, s)] (first visit: either point of w);
+//   a once-visited w keeps its label s: child (m with w twice), slot (w, s) =
+//   acc[(w, s)];
+//   close: t_m = W sum_rows acc[(u, s_u)]; the next cycle opens at the lowest
+//   once-visited vertex h with its label s_h (slot (h, s_h) of row (m', h, s_h)),
+//   or S = t_m at the full mask.
+#include "cos_device.hpp"
+
+namespace libcos {
+
+template <int N>
+struct SubRec {
+    int code, rb;
+    uint32_t ones, twos, subb;
+    int crb[2 * N];
+};
+
+template <int N>
+__device__ __forceinline__ SubRec<N> load_sub_rec(const DevPlan &P, int gi) {
+    const cint32 *r = (const cint32 *)(P.mrec + (int64_t)gi * kSubRecInts);
+    SubRec<N> m;
+    m.code = r[0];
+    const uint32_t info = (uint32_t)r[1];
+    m.ones = info & 0xffffu;
+    m.twos = info >> 16;
+    m.rb = r[2];
+    m.subb = (uint32_t)r[3];
+#pragma unroll
+    for (int i = 0; i < 2 * N; ++i) m.crb[i] = r[4 + i];
+    return m;
+}
+
+// child row base for visiting slot i = 2w + s (i wave-uniform; select chain
+// keeps the record in scalar registers)
+template <int N>
+__device__ __forceinline__ int sub_child_base(const SubRec<N> &M, int i) {
+    int rb = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * N; ++k) rb = (k == i) ? M.crb[k] : rb;
+    return rb;
+}
+
+template <int N>
+__device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
+                                            double *__restrict__ nxt, uint32_t lane8, int64_t cpl, int64_t npl,
+                                            int lam, int u, int su, int r, bool start, double &cp, double &dext) {
+    constexpr int D = 2 * N;
+    const uint32_t ones = M.ones, twos = M.twos, subb = M.subb;
+    const uint32_t cs = sub_current(N, u, su, ones, twos, subb);
+    const double *__restrict__ src = cur + lam * cpl + (int64_t)r * D * 64;
+    asm volatile("" : "+v"(gaddr));
+    const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
+    double f[D], acc[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) f[i] = ((cs >> i) & 1u) ? lane_ld(src + i * 64, lane8) : 0.0;
+    if (start) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) f[i] = i == su ? 1.0 : 0.0;   // start: vertex 0 on label s_u
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j) acc[j] = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int j = 0; j < D; ++j) acc[j] = __builtin_fma(f[i], Gs[(i * D + j) * 64], acc[j]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+        if (j == 2 * u + su) cp += acc[j];
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+        const uint32_t bit = 1u << w;
+        if (twos & bit) continue;
+        if (!(ones & bit)) {
+            // first visit, on either label; the child's heads are the parent's
+            const int hs = sub_head_slot(u, su, twos);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int crow = M.crb[2 * w + s] + hs;
+                lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * w + s) * 64, lane8, 2.0 * acc[2 * w + s]);
+            }
+        } else {
+            const int s = (subb >> w) & 1u;
+            const double val = s ? acc[2 * w + 1] : acc[2 * w];
+            if (w == 0 && u == 0) {
+                dext = val;   // vertex 0 once visited: the next cycle opens on this same slot
+                continue;
+            }
+            const int crow = (s ? M.crb[2 * w + 1] : M.crb[2 * w]) + sub_head_slot(u, su, twos | bit);
+            lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * w + s) * 64, lane8, val);
+        }
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void sub_fwd_close(const SubRec<N> &M, double *__restrict__ nxt, uint32_t lane8,
+                                              int64_t npl, int lam, double t, double dext) {
+    constexpr int D = 2 * N;
+    const int h = __builtin_ctz(M.ones);
+    const int sh = (M.subb >> h) & 1u;
+    const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, M.twos | (1u << h));
+    lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * h + sh) * 64, lane8, t + (h == 0 ? dext : 0.0));
+}
+
+template <int N, bool MULTI>
+__global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
+    constexpr int D = 2 * N;
+    extern __shared__ double lds[];
+    double *Gs_all = lds;                      // [D * D][64]
+    const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
+    const int wpb = blockDim.x >> 6;
+    const DevPlan &P = A.plan;
+    const int4 L = load_level(P, A.level);
+    const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
+    const int mb1 = min(mb0 + A.mpb, L.w);     // may be empty: the wave still joins the barriers
+    const int gl = blockIdx.y, g = A.group0 + gl;
+    const int nfs = A.nfs;
+    const double *__restrict__ cur = A.cur + gl * A.cur_gstride + (int64_t)A.cur_row0 * D * 64;
+    double *__restrict__ nxt = A.nxt + gl * A.nxt_gstride + (int64_t)A.nxt_row0 * D * 64;
+    const int64_t cpl = A.cur_frows * D * 64, npl = A.nxt_frows * D * 64;
+    const uint32_t lane8 = (uint32_t)lane * 8u;
+    const uint32_t gaddr = lds_addr(Gs_all) + lane * 8u;
+    const int cfg = A.lane_cfg[g * 64 + lane];
+    const bool last = A.level == 2 * N, start = A.level == 1;
+    constexpr int K = MULTI ? kMultiMasks : 1;
+    double cpk[K];   // MULTI: close sum of each of the wave's masks, over rows and flavours
+#pragma unroll
+    for (int k = 0; k < K; ++k) cpk[k] = 0.0;
+
+    for (int lam = 0; lam < nfs; ++lam) {
+        __syncthreads();
+        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * D * D * 64;
+        for (int i = threadIdx.x; i < D * D * 64; i += blockDim.x) Gs_all[i] = gsrc[i];
+        __syncthreads();
+        const int mend = MULTI ? min(mb1, mb0 + K) : mb1;
+#pragma unroll
+        for (int k = 0; k < (MULTI ? K : 1); ++k) {
+            for (int mi = mb0 + k; mi < mend; mi += (MULTI ? K : 1)) {
+                const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
+                const uint32_t ones = M.ones, twos = M.twos;
+                const bool full0 = twos & 1u;            // vertex 0 visited twice: rows come in label pairs
+                uint32_t hs = full0 ? (twos & ~1u) : 0u;  // heads >= 1, ascending
+                int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
+                double cp = 0.0, dext = 0.0;
+                while (true) {
+                    sub_fwd_row<N>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, su, M.rb + slot, start, cp, dext);
+                    ++slot;
+                    if (full0 && su == 0) {
+                        su = 1;
+                        continue;
+                    }
+                    if (!hs) break;
+                    u = __builtin_ctz(hs);
+                    hs &= hs - 1u;
+                    su = 0;
+                }
+                if (MULTI) {
+                    cpk[k] += cp;
+                    if (!last && (ones & 1u)) sub_fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
+                } else {
+                    const double t = A.W * cp;
+                    if (last) {
+                        if (cfg >= 0 && A.out) A.out[cfg] = t;
+                    } else if (ones) {
+                        sub_fwd_close<N>(M, nxt, lane8, npl, 0, t, dext);
+                    }
+                }
+            }
+        }
+    }
+    if (MULTI) {
+        // t_m = W sum over rows and flavours; the next cycle opens in every flavour
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int mi = mb0 + k;
+            if (mi >= mb1) continue;
+            const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
+            const double t = A.W * cpk[k];
+            if (last) {
+                if (cfg >= 0 && A.out) A.out[cfg] = t;
+            } else if (M.ones) {
+                const int h = __builtin_ctz(M.ones);
+                const int sh = (M.subb >> h) & 1u;
+                const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, M.twos | (1u << h));
+                double *dst = nxt + (int64_t)crow * D * 64 + (2 * h + sh) * 64;
+                for (int lam = 0; lam < nfs; ++lam) {
+                    // h = 0: the slot holds this wave's own extension value (written above)
+                    const double x = h == 0 ? lane_ld(dst + lam * npl, lane8) : 0.0;
+                    lane_st(dst + lam * npl, lane8, t + x);
+                }
+            }
+        }
+    }
+}
+
+static hipError_t allow_sub_lds(const void *fn, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s) {
+    const int n = a.plan.n;
+    if (wpb < 1 || wpb > 16) return hipErrorInvalidValue;
+    const bool multi = a.nfs > 1;
+    if (multi && a.mpb > kMultiMasks) return hipErrorInvalidValue;
+    const size_t shm = (size_t)(2 * n) * (2 * n) * 64 * sizeof(double);
+    const dim3 grid((unsigned)((nblocks + wpb - 1) / wpb), (unsigned)ngroups);
+    switch (n) {
+#define COS_SUB_CASE(K)                                                                                  \
+    case K: {                                                                                            \
+        hipError_t e = multi ? allow_sub_lds((const void *)sub_fwd_kernel<K, true>, shm)                 \
+                             : allow_sub_lds((const void *)sub_fwd_kernel<K, false>, shm);               \
+        if (e != hipSuccess) return e;                                                                   \
+        if (multi) hipLaunchKernelGGL((sub_fwd_kernel<K, true>), grid, dim3(64 * wpb), shm, s, a);       \
+        else hipLaunchKernelGGL((sub_fwd_kernel<K, false>), grid, dim3(64 * wpb), shm, s, a);            \
+        break;                                                                                           \
+    }
+        COS_SUB_CASE(1) COS_SUB_CASE(2) COS_SUB_CASE(3) COS_SUB_CASE(4)
+        COS_SUB_CASE(5) COS_SUB_CASE(6) COS_SUB_CASE(7) COS_SUB_CASE(8)
+#undef COS_SUB_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace libcos

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "cos_internal.hpp"
@@ -52,7 +53,9 @@ struct HostPlan {
     std::vector<int2> rows;
     std::vector<int32_t> masks;
     std::vector<int4> levels;       // [2n + 2]
-    std::vector<int32_t> mrec;      // [masks][kRecInts]
+    std::vector<int32_t> mrec;      // [masks][rec_ints]
+    bool sub = false;               // sublattice-labelled state space
+    int rec_ints = kRecInts;
     int32_t max_rows = 0, max_masks = 0;
     int64_t states = 0, ext = 0, closes = 0, shift_edges = 0;
 };
@@ -129,21 +132,114 @@ void build_host_plan(int n, HostPlan &P) {
     }
 }
 
+// The sublattice-labelled plan (mask digits base 4; see cos_internal.hpp).
+void build_host_plan_sub(int n, HostPlan &P) {
+    P.n = n;
+    P.sub = true;
+    P.rec_ints = kSubRecInts;
+    int N4 = 1;
+    for (int k = 0; k < n; ++k) N4 *= 4;
+    P.rowbase.assign(N4, -1);
+    P.minfo.assign(N4, 0);
+    std::vector<uint32_t> subb(N4, 0);
+    std::vector<std::vector<int32_t>> bylevel(2 * n + 2);
+    for (int code = 0; code < N4; ++code) {
+        uint32_t ones = 0, twos = 0, sb = 0;
+        int c = code, lvl = 0;
+        for (int k = 0; k < n; ++k) {
+            const int d = c & 3;
+            c >>= 2;
+            if (d == 1 || d == 2) ones |= 1u << k, lvl += 1;
+            if (d == 2) sb |= 1u << k;
+            if (d == 3) twos |= 1u << k, lvl += 2;
+        }
+        P.minfo[code] = ones | (twos << 16);
+        subb[code] = sb;
+        if (!((ones | twos) & 1u)) continue;   // vertex 0 is always visited
+        bylevel[lvl].push_back(code);
+    }
+    P.levels.assign(2 * n + 2, make_int4(0, 0, 0, 0));
+    for (int l = 1; l <= 2 * n; ++l) {
+        int4 L;
+        L.x = (int)P.rows.size();
+        L.z = (int)P.masks.size();
+        int r = 0, mi = 0;
+        for (int code : bylevel[l]) {
+            const uint32_t ones = P.minfo[code] & 0xffffu, twos = P.minfo[code] >> 16;
+            P.rowbase[code] = r;
+            P.masks.push_back(code);
+            // rows: (0, s_0) alone, or label pairs for head 0 and every h >= 1 visited twice
+            std::vector<std::pair<int, int>> heads;
+            if (!(twos & 1u)) {
+                heads.push_back({0, (int)(subb[code] & 1u)});
+            } else {
+                heads.push_back({0, 0});
+                heads.push_back({0, 1});
+                for (int h = 1; h < n; ++h)
+                    if ((twos >> h) & 1u) heads.push_back({h, 0}), heads.push_back({h, 1});
+            }
+            for (auto [u, su] : heads) {
+                P.rows.push_back(make_int2(code, 2 * u + su));
+                const uint32_t cs = sub_current(n, u, su, ones, twos, subb[code]);
+                int edges = 0;   // per state: one child per open vertex and admissible label
+                for (int w = 0; w < n; ++w) {
+                    if ((twos >> w) & 1u) continue;
+                    edges += ((ones >> w) & 1u) ? 1 : 2;
+                }
+                const int cnt = __builtin_popcount(cs);
+                P.states += cnt;
+                P.ext += (int64_t)cnt * edges;
+                ++r;
+            }
+            ++mi;
+        }
+        L.y = r;
+        L.w = mi;
+        P.levels[l] = L;
+        P.max_rows = std::max(P.max_rows, r);
+        P.max_masks = std::max(P.max_masks, mi);
+    }
+    P.closes = P.states;
+    P.levels[2 * n + 1] = make_int4((int)P.rows.size(), 0, (int)P.masks.size(), 0);
+    P.mrec.assign(P.masks.size() * kSubRecInts, -1);
+    int p4[kSubNmax + 1];
+    p4[0] = 1;
+    for (int k = 1; k <= kSubNmax; ++k) p4[k] = 4 * p4[k - 1];
+    for (size_t i = 0; i < P.masks.size(); ++i) {
+        const int code = P.masks[i];
+        int32_t *r = &P.mrec[i * kSubRecInts];
+        r[0] = code;
+        r[1] = (int32_t)P.minfo[code];
+        r[2] = P.rowbase[code];
+        r[3] = (int32_t)subb[code];
+        for (int w = 0; w < n; ++w) {
+            const int d = (code / p4[w]) & 3;
+            if (d == 0) {
+                r[4 + 2 * w] = P.rowbase[code + p4[w]];          // -> once on A
+                r[4 + 2 * w + 1] = P.rowbase[code + 2 * p4[w]];  // -> once on B
+            } else if (d != 3) {
+                r[4 + 2 * w + (d - 1)] = P.rowbase[code + (3 - d) * p4[w]];   // -> twice, label kept
+            }
+        }
+    }
+}
+
 struct DevTables {
     DevPlan dp{};
     void *mem = nullptr;
 };
 
 std::mutex g_mu;
-std::map<std::pair<int, int>, std::shared_ptr<HostPlan>> g_host;   // (n, 0)
-std::map<std::pair<int, int>, DevTables> g_dev;                    // (device, n)
+std::map<std::pair<int, int>, std::shared_ptr<HostPlan>> g_host;   // (n, sublattice)
+std::map<std::tuple<int, int, int>, DevTables> g_dev;              // (device, n, sublattice)
 
-std::shared_ptr<HostPlan> host_plan(int n) {
-    auto key = std::make_pair(n, 0);
+std::shared_ptr<HostPlan> host_plan(int n, bool sub = false) {
+    auto key = std::make_pair(n, sub ? 1 : 0);
     auto it = g_host.find(key);
     if (it != g_host.end()) return it->second;
     auto p = std::make_shared<HostPlan>();
-    build_host_plan(n, *p);
+    if (sub) build_host_plan_sub(n, *p);
+    else build_host_plan(n, *p);
     g_host[key] = p;
     return p;
 }
@@ -154,15 +250,15 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 // concurrent workgroups instead of more memory
 constexpr int64_t kWorkspaceCap = (int64_t)24 << 30;
 
-cos_status device_plan(int dev, int n, DevPlan *out) {
+cos_status device_plan(int dev, int n, bool sub, DevPlan *out) {
     std::lock_guard<std::mutex> lk(g_mu);
-    auto key = std::make_pair(dev, n);
+    auto key = std::make_tuple(dev, n, sub ? 1 : 0);
     auto it = g_dev.find(key);
     if (it != g_dev.end()) {
         *out = it->second.dp;
         return COS_OK;
     }
-    auto hp = host_plan(n);
+    auto hp = host_plan(n, sub);
     const size_t s1 = align_up(hp->mrec.size() * 4), s2 = align_up(hp->levels.size() * sizeof(int4));
     char *mem = nullptr;
     if (hipMalloc((void **)&mem, s1 + s2) != hipSuccess)
@@ -202,7 +298,10 @@ cos_status check_device(int *dev, int *ncu) {
 cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
     if (variant != COS_UNIFORM && variant != COS_FLAVOUR)
         return fail(COS_EINVAL, "variant must be COS_UNIFORM (0) or COS_FLAVOUR (1), got %d", variant);
-    if (flags & ~COS_F_STUBS) return fail(COS_EINVAL, "unknown flag bits 0x%x", flags & ~COS_F_STUBS);
+    if (flags & ~(COS_F_STUBS | COS_F_SUBLATTICE))
+        return fail(COS_EINVAL, "unknown flag bits 0x%x", flags & ~(COS_F_STUBS | COS_F_SUBLATTICE));
+    if ((flags & COS_F_STUBS) && (flags & COS_F_SUBLATTICE))
+        return fail(COS_EINVAL, "COS_F_STUBS cannot be combined with COS_F_SUBLATTICE");
     if (nflav < 1 || nflav > COS_FMAX) return fail(COS_ERANGE, "nflav must be in [1, %d], got %d", COS_FMAX, nflav);
     return COS_OK;
 }
@@ -211,7 +310,7 @@ cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
 
 // launch shape of the level kernels of one order
 struct LaunchShape {
-    int fwd_wpb = 8;    // forward: wavefronts per workgroup (<= 8)
+    int fwd_wpb = 8;    // forward: wavefronts per workgroup (<= 8; sublattice: <= 16, default 16)
     int fwd_cap = 0;    // forward: most masks per wavefront (0: by flavour count)
     int adj_cap = 8;    // reverse: most masks per wavefront
 };
@@ -224,7 +323,9 @@ struct OrderGroup {
     int chunk_fwd = 1, chunk_adj = 1;  // groups per chunk (bounded workspace)
     int64_t gb_off = 0, sb_off = 0;    // offsets into the packed gradient accumulators
     LaunchShape shape;                 // launch shape of the level kernels (autotuned)
+    bool sub = false;                  // sublattice-labelled states (2n slots per row)
     std::shared_ptr<HostPlan> hp;
+    int slots() const { return sub ? 2 * n : n; }
 };
 
 struct cos_batch_s {
@@ -300,6 +401,23 @@ cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int6
     return COS_OK;
 }
 
+cos_status cos_plan_counts_sublattice(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
+                                      int64_t *masks, int64_t *rows) {
+    if (n < 1 || n > COS_NMAX_SUBLATTICE)
+        return fail(COS_ERANGE, "n must be in [1, %d], got %d", COS_NMAX_SUBLATTICE, n);
+    std::shared_ptr<HostPlan> p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        p = host_plan(n, true);
+    }
+    if (states) *states = p->states;
+    if (extensions) *extensions = p->ext;
+    if (closes) *closes = p->closes;
+    if (masks) *masks = (int64_t)p->masks.size();
+    if (rows) *rows = (int64_t)p->rows.size();
+    return COS_OK;
+}
+
 cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int32_t variant,
                             int32_t flags, cos_batch_t *out) {
     if (!out) return fail(COS_EINVAL, "out is NULL");
@@ -308,9 +426,11 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
     if (!n) return fail(COS_EINVAL, "n is NULL");
     cos_status st = check_common(nflav, variant, flags);
     if (st) return st;
+    const bool sub = (flags & COS_F_SUBLATTICE) != 0;
+    const int nmax = sub ? COS_NMAX_SUBLATTICE : COS_NMAX;
     for (int32_t c = 0; c < nconf; ++c)
-        if (n[c] < 1 || n[c] > COS_NMAX)
-            return fail(COS_ERANGE, "n[%d] = %d outside [1, %d]", c, n[c], COS_NMAX);
+        if (n[c] < 1 || n[c] > nmax)
+            return fail(COS_ERANGE, "n[%d] = %d outside [1, %d]", c, n[c], nmax);
     int dev = 0, ncu = 0;
     if ((st = check_device(&dev, &ncu))) return st;
 
@@ -329,7 +449,7 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
     for (int c = 0; c < nconf; ++c) seen[n[c]] = true;
     for (int k = 1; k <= COS_NMAX; ++k)
         if (seen[k]) {
-            if ((st = device_plan(dev, k, &b->plans[k]))) return st;
+            if ((st = device_plan(dev, k, sub, &b->plans[k]))) return st;
         }
     b->uniform_n = std::all_of(n, n + nconf, [&](int32_t x) { return x == n[0]; });
 
@@ -349,15 +469,17 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
         o.gt_off = gt;
         o.sig_off = sg;
         o.lane_off = ln;
+        o.sub = sub;
+        if (sub) o.shape.fwd_wpb = 16;   // (2n)^2 matrices in LDS: one workgroup per CU, make it wide
         {
             std::lock_guard<std::mutex> lk(g_mu);
-            o.hp = host_plan(o.n);
+            o.hp = host_plan(o.n, sub);
         }
-        const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
         const int64_t per_group = 2 * (int64_t)o.hp->max_rows * rs;
         o.chunk_fwd = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
         win = std::max(win, per_group * o.chunk_fwd);
-        gt += (int64_t)o.ngroups * b->nfs * o.n * o.n * 64;
+        gt += (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
         sg += (int64_t)o.ngroups * b->nfs * 64;
         ln += (int64_t)o.ngroups * 64;
         b->orders.push_back(o);
@@ -410,7 +532,7 @@ static PackArgs pack_args(cos_batch_t b, const OrderGroup &o, const double *d_G,
     p.GT = b->d_GT + o.gt_off;
     p.sigT = b->d_sigT + o.sig_off;
     p.lane_cfg = b->d_lane + o.lane_off;
-    p.n = o.n;
+    p.n = o.slots();   // matrix side: n, or 2n with sublattice labels
     p.nfs = b->nfs;
     p.nmat = b->nmat;
     p.nstub = b->nstub;
@@ -458,7 +580,7 @@ static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double
     HIP_TRY(tmark(b, COS_PHASE_PACK, s));
     HIP_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
     HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
-    const int64_t rs = (int64_t)b->nfs * o.n * 64;
+    const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
     const int64_t gstride = (int64_t)o.hp->max_rows * rs;
     for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_fwd) {
         const int cg = std::min(o.chunk_fwd, o.ngroups - c0);
@@ -474,7 +596,8 @@ static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double
             const int nm = o.hp->levels[l].w;
             a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
             a.out = d_out;
-            HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            if (o.sub) HIP_TRY(launch_sub_level(a, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            else HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
         }
     }
     return COS_OK;
@@ -589,6 +712,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
     if (st) return st;
     if (!d_out_bar || !d_G_bar) return fail(COS_EINVAL, "d_out_bar and d_G_bar are required");
     if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
+    if (b->flags & COS_F_SUBLATTICE) return fail(COS_EUNSUPPORTED, "the reverse sweep of sublattice batches is not built");
     if ((st = prepare_adjoint(b))) return st;
     hipStream_t s = (hipStream_t)stream;
     for (const OrderGroup &o : b->orders)
@@ -638,13 +762,15 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
     hipStream_t s = (hipStream_t)stream;
     const bool was_timing = b->timing;
     b->timing = false;
-    static const int kWaves[] = {4, 8};
+    if (d_out_bar && (b->flags & COS_F_SUBLATTICE))
+        return fail(COS_EUNSUPPORTED, "the reverse sweep of sublattice batches is not built");
+    static const int kWaves[] = {4, 8}, kSubWaves[] = {8, 16};
     static const int kCaps[] = {1, 2, 4, 8, 16};
     for (OrderGroup &o : b->orders) {
         // forward: waves per workgroup x masks per wavefront
         LaunchShape best = o.shape;
         float tbest = 1e30f;
-        for (int wv : kWaves)
+        for (int wv : (o.sub ? kSubWaves : kWaves))
             for (int cap : kCaps) {
                 o.shape.fwd_wpb = wv;
                 o.shape.fwd_cap = cap;
@@ -780,7 +906,7 @@ cos_status cos_release(void) {
     for (auto &kv : g_dev) {
         int cur = 0;
         (void)hipGetDevice(&cur);
-        (void)hipSetDevice(kv.first.first);
+        (void)hipSetDevice(std::get<0>(kv.first));
         (void)hipFree(kv.second.mem);
         (void)hipSetDevice(cur);
     }

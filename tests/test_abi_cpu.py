@@ -44,6 +44,17 @@ def test_plan_counts_match_golden(B, n):
     assert c["rows"] == 2 * 3 ** (n - 1) + (n - 1) * 3 ** max(n - 2, 0) * (1 if n >= 2 else 0)
 
 
+@pytest.mark.parametrize("n", range(1, 7))
+def test_sublattice_plan_counts_match_oracle(B, n):
+    """The labelled state space the library plans (closed-form rows and current
+    slots) against the oracle's breadth-first enumeration."""
+    from oracle import sublattice
+    c = B.plan_counts_sublattice(n)
+    o = sublattice.plan_counts(n)
+    assert (c["states"], c["ext"], c["closes"], c["masks"], c["rows"]) == \
+        (o["states"], o["ext"], o["closes"], o["masks"], o["rows"])
+
+
 def _st(B, code):
     return B.lib.cos_status_string(code).decode()
 
@@ -62,6 +73,10 @@ def test_argument_validation_without_device(B):
     assert lib.cos_batch_create(2, n.ctypes.data, 17, 0, 0, ctypes.byref(h)) == -2
     assert lib.cos_batch_create(2, n.ctypes.data, 2, 7, 0, ctypes.byref(h)) == -1
     assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 8, ctypes.byref(h)) == -1
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 3, ctypes.byref(h)) == -1   # shifts with sublattices
+    big = np.array([4, 9], dtype=np.int32)
+    assert lib.cos_batch_create(2, big.ctypes.data, 2, 0, 2, ctypes.byref(h)) == -2  # above the sublattice max
+    assert lib.cos_plan_counts_sublattice(9, None, None, None, None, None) == -2
     bad = np.array([4, 13], dtype=np.int32)
     assert lib.cos_batch_create(2, bad.ctypes.data, 2, 0, 0, ctypes.byref(h)) == -2
     assert "n[1] = 13" in lib.cos_last_error().decode()

@@ -85,3 +85,23 @@ def test_adjoint_workload(oracle_mod):
         fd_d = (S_shift(h) - S_shift(-h)) / (2 * h)
         got = res["alb"][c, 0] / w.nflav
         assert abs(got - fd_d) <= 1e-6 * max(abs(fd_d), 1e-3 * sabs_S), (c, got, fd_d)
+
+
+@pytest.mark.parametrize("n,nf,variant", [(12, 2, 0), (11, 2, 1)])
+def test_adjoint_large_order(oracle_mod, n, nf, variant):
+    """Reverse sweep at the largest orders (n = COS_NMAX, and n = 11 with two
+    flavour matrices), with shifts, against the oracle's reverse sweep."""
+    announce("adjoint n=%d nf=%d variant=%d" % (n, nf, variant))
+    rng = np.random.default_rng(1000 + n)
+    nmat = 1 if variant == 0 else nf
+    M = rng.normal(size=(nmat, n, n)) * 0.5
+    st = rng.normal(size=(1, nmat)) * 0.3
+    S, S2, Gb, sb = gpu_forward([M], nf, variant, st, adjoint=True, out_bar=np.array([0.7]))
+    assert np.array_equal(S, S2)
+    Sref, gref, sref = oracle_mod.dp_adjoint(oracle_args(M, variant), nf, variant, st[0])
+    Sabs, gabs, sabs = oracle_mod.dp_adjoint(np.abs(oracle_args(M, variant)), nf, variant, -np.abs(st[0]), 1.0)
+    tol = 8 * n * (n + 2) * EPS
+    assert abs(S[0] - Sref) <= tol * Sabs
+    gg = Gb[0][0] if variant == 0 else Gb[0]
+    assert np.all(np.abs(gg - 0.7 * gref) <= 0.7 * tol * np.abs(gabs) + 1e-300)
+    assert np.all(np.abs(sb[0] - 0.7 * sref) <= 0.7 * tol * np.abs(sabs) + 1e-300)

@@ -1,0 +1,120 @@
+"""Sublattice-summed connected sums on the GPU (bipartite lattices,
+COS_F_SUBLATTICE) against the oracle's sum over label assignments.
+
+Tolerance: as for the unlabelled sum, |S_gpu - S| <= 8 n (n + 2) eps S_abs,
+with S_abs the oracle's labelled sum over absolute values (|A|, |w|)."""
+import numpy as np
+import pytest
+
+from gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _run(mats, nflav, variant, w=-1.0, tune=False):
+    """mats: list of (nmat, 2n, 2n) arrays -> S per configuration (GPU)."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    n = np.array([m.shape[-1] // 2 for m in mats], dtype=np.int32)
+    sizes = np.array([m.size for m in mats], dtype=np.int64)
+    off = np.zeros(len(mats), dtype=np.int64)
+    off[1:] = np.cumsum(sizes[:-1])
+    G = torch.as_tensor(np.concatenate([m.reshape(-1) for m in mats]), device="cuda:0")
+    Goff = torch.as_tensor(off, device="cuda:0")
+    b = B.Batch(n, nflav, variant, sublattice=True)
+    out = torch.full((len(mats),), float("nan"), dtype=torch.float64, device="cuda:0")
+    if tune:
+        b.autotune(G, Goff, None, w, out)
+        out.fill_(float("nan"))
+    b.forward(G, Goff, None, w, out)
+    torch.cuda.synchronize()
+    shape = b.launch_shape(int(n[0]))
+    b.close()
+    return out.cpu().numpy(), shape
+
+
+def _ref(A, nf, variant, w=-1.0):
+    from oracle import sublattice as SL
+    M = A[0] if variant == 0 else A
+    return SL.by_assignment(M, nf, variant, w), SL.by_assignment(np.abs(M), nf, variant, abs(w))
+
+
+@pytest.mark.parametrize("nf,variant", [(2, 0), (3, 0), (2, 1), (3, 1)])
+def test_random_batch(oracle_mod, nf, variant):
+    announce("sublattice random batch nf=%d variant=%d" % (nf, variant))
+    rng = np.random.default_rng(500 + 10 * nf + variant)
+    orders = [1, 2, 3, 4, 5, 6, 3, 5, 7]
+    nmat = 1 if variant == 0 else nf
+    mats = [rng.normal(size=(nmat, 2 * k, 2 * k)) * 0.5 for k in orders]
+    S, _ = _run(mats, nf, variant)
+    for i, A in enumerate(mats):
+        n = orders[i]
+        ref, sabs = _ref(A, nf, variant)
+        assert abs(S[i] - ref) <= 8 * n * (n + 2) * EPS * sabs, (i, n, S[i], ref, sabs)
+
+
+def test_max_order(oracle_mod):
+    """n = 8 (the largest labelled order), two flavour matrices."""
+    announce("sublattice n=8, flavour variant")
+    rng = np.random.default_rng(808)
+    A = rng.normal(size=(2, 16, 16)) * 0.4
+    S, _ = _run([A], 2, 1)
+    ref, sabs = _ref(A, 2, 1)
+    assert abs(S[0] - ref) <= 8 * 8 * 10 * EPS * sabs, (S[0], ref, sabs)
+
+
+def test_label_independent_matrices_give_2n_times_plain():
+    """A[(k,s),(j,t)] = G[k][j]: every one of the 2^n labellings gives the
+    unlabelled sum, computed here by the unlabelled kernels."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("sublattice: label-independent matrices, orders 5..8")
+    rng = np.random.default_rng(77)
+    orders = [8, 6, 5, 8, 7]
+    Gs = [rng.normal(size=(k, k)) * 0.5 for k in orders]
+    mats = [np.repeat(np.repeat(G, 2, axis=0), 2, axis=1)[None] for G in Gs]
+    S, _ = _run(mats, 3, 0)
+    flat = torch.as_tensor(np.concatenate([G.reshape(-1) for G in Gs]), device="cuda:0")
+    off = np.zeros(len(Gs), dtype=np.int64)
+    off[1:] = np.cumsum([G.size for G in Gs][:-1])
+    b = B.Batch(orders, 3, 0)
+    P = torch.empty(len(Gs), dtype=torch.float64, device="cuda:0")
+    Pa = torch.empty_like(P)
+    b.forward(flat, torch.as_tensor(off, device="cuda:0"), None, -1.0, P)
+    flat_abs = flat.abs()
+    b.forward(flat_abs, torch.as_tensor(off, device="cuda:0"), None, 1.0, Pa)
+    torch.cuda.synchronize()
+    b.close()
+    for i, k in enumerate(orders):
+        assert abs(S[i] - 2 ** k * float(P[i])) <= 2 * 8 * k * (k + 2) * EPS * 2 ** k * float(Pa[i]), (k, S[i], P[i])
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 6, 7])
+def test_counts(n):
+    """All propagators 1, w = +1, one flavour: 2^n c_n(1), exact."""
+    from oracle import counts
+    announce("sublattice counts n=%d" % n)
+    S, _ = _run([np.ones((1, 2 * n, 2 * n))], 1, 0, w=1.0)
+    assert S[0] == float(2 ** n * counts.connected_counts(n, 1)[n]), (n, S[0])
+
+
+def test_autotune_and_unsupported_reverse():
+    """Autotuning the labelled forward keeps S bitwise; the reverse sweep of a
+    labelled batch is reported as unsupported."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("sublattice autotune; adjoint unsupported")
+    rng = np.random.default_rng(5)
+    mats = [rng.normal(size=(1, 12, 12)) * 0.5 for _ in range(70)]
+    S0, _ = _run(mats, 2, 0)
+    S1, shape = _run(mats, 2, 0, tune=True)
+    assert np.array_equal(S0, S1)
+    assert shape["fwd_waves"] in (8, 16), shape
+    b = B.Batch([6], 2, 0, sublattice=True)
+    G = torch.zeros(144, dtype=torch.float64, device="cuda:0")
+    out = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(B.CosError) as e:
+        b.adjoint(G, None, None, -1.0, torch.ones_like(out), out, torch.empty_like(G), None)
+    assert e.value.status == -5
+    b.close()
