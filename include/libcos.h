@@ -135,6 +135,24 @@ cos_status cos_build_g0(int32_t nconf, const int32_t *d_n, const int64_t *d_voff
                         double beta, int32_t nmat, const double *mu, const double *alpha,
                         const int64_t *d_Goff, double *d_G, double *d_dG, void *stream);
 
+/* Free propagator matrices of the honeycomb lattice for COS_F_SUBLATTICE
+ * batches (Methods, honeycomb model): per matrix g the Bloch Hamiltonian
+ * H_g(k) = [[delta[g] - (mu[g] - alpha[g]), eps(k)], [conj(eps(k)),
+ * -delta[g] - (mu[g] - alpha[g])]] with eps(k) = -t (1 + e^{i k.b1} +
+ * e^{i k.b2}) on the L x L grid k.b_i = 2 pi m_i / L (sublattice A of cell R
+ * hops to B of R, R + b1, R + b2); G(k, tau) = -exp(-H tau)(1 - nF(H)) for
+ * tau > 0 and exp(-H tau) nF(H) for tau <= 0 (an equal-time pair is 0^-);
+ * entry [2a+p][2b+q] = L^-2 sum_k e^{i k.(R_a - R_b)} G_pq(k, tau_a - tau_b).
+ * d_cells: int32 [sum n][2] unit-cell coordinates in [0, L), 1 <= L <= 32;
+ * d_tau [sum n]; d_voff[c]: first vertex of config c; mu, alpha, delta: HOST
+ * arrays [nmat].  Output: nmat matrices of side 2 n_c per configuration at
+ * d_G[d_Goff[c] + (g*2n_c + i)*2n_c + j].  The equal-time shift the CoS
+ * formulation puts on the diagonal is left to the caller. */
+cos_status cos_build_g0_honeycomb(int32_t nconf, const int32_t *d_n, const int64_t *d_voff,
+                                  const int32_t *d_cells, const double *d_tau, int32_t L, double t,
+                                  double beta, int32_t nmat, const double *mu, const double *alpha,
+                                  const double *delta, const int64_t *d_Goff, double *d_G, void *stream);
+
 /* Chain rule to the chemical potential and the shift (Methods: xi = eps -
  * mu + alpha, shift weight sigma = alpha / U).  Per configuration c and
  * matrix g: xb = sum_kj G_bar[g][k][j] * dG[g][k][j];

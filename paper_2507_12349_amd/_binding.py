@@ -24,7 +24,7 @@ EXPORTED = (
     "cos_connected_sum_adjoint", "cos_connected_sum", "cos_build_g0", "cos_chain_mu_shift",
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
-    "cos_plan_counts_sublattice",
+    "cos_plan_counts_sublattice", "cos_build_g0_honeycomb",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -50,6 +50,7 @@ def _load():
         "cos_chain_mu_shift": ([i32, p, i32, p, p, p, p, i32, d, p, p, p], i32),
         "cos_plan_counts": ([i32, P64, P64, P64, P64, P64, P64], i32),
         "cos_plan_counts_sublattice": ([i32, P64, P64, P64, P64, P64], i32),
+        "cos_build_g0_honeycomb": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p], i32),
         "cos_status_string": ([i32], ctypes.c_char_p),
         "cos_last_error": ([], ctypes.c_char_p),
         "cos_release": ([], i32),
@@ -203,6 +204,18 @@ def build_g0(nconf, n, voff, sites, tau, L, t, beta, mu, alpha, Goff, G, dG=None
     _check(lib.cos_build_g0(int(nconf), _ptr(n), _ptr(voff), _ptr(sites), _ptr(tau), int(L), float(t),
                             float(beta), int(mu.size), _ptr(mu), _ptr(alpha), _ptr(Goff), _ptr(G), _ptr(dG),
                             _stream(stream)), "cos_build_g0")
+
+
+def build_g0_honeycomb(nconf, n, voff, cells, tau, L, t, beta, mu, alpha, delta, Goff, G, stream=None):
+    """Device honeycomb propagator builder (2n x 2n matrices, index 2k + s);
+    n, voff, cells, tau, Goff, G are device tensors, mu, alpha, delta host
+    sequences of length nmat."""
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
+    alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(-1))
+    delta = np.ascontiguousarray(np.asarray(delta, dtype=np.float64).reshape(-1))
+    _check(lib.cos_build_g0_honeycomb(int(nconf), _ptr(n), _ptr(voff), _ptr(cells), _ptr(tau), int(L), float(t),
+                                      float(beta), int(mu.size), _ptr(mu), _ptr(alpha), _ptr(delta), _ptr(Goff),
+                                      _ptr(G), _stream(stream)), "cos_build_g0_honeycomb")
 
 
 def chain_mu_shift(nconf, n, nmat, Goff, G_bar, dG, stub_bar, nstub, U, mu_bar, alpha_bar, stream=None):

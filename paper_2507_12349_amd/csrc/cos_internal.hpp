@@ -154,6 +154,10 @@ constexpr int kMultiMasks = 4;
 hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int32_t *sites,
                      const double *tau, int L, double t, double beta, int nmat, const double *mu,
                      const double *alpha, const int64_t *Goff, double *G, double *dG, hipStream_t s);
+hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff, const int32_t *cells,
+                               const double *tau, int L, double t, double beta, int nmat, const double *mu,
+                               const double *alpha, const double *delta, const int64_t *Goff, double *G,
+                               hipStream_t s);
 hipError_t launch_chain(int nconf, const int32_t *n, int nmat, const int64_t *Goff, const double *Gb,
                         const double *dG, const double *sb, int nstub, double U, double *mub,
                         double *alb, hipStream_t s);

@@ -90,6 +90,110 @@ hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int
 }
 
 // ---------------------------------------------------------------------------
+// free propagator of the honeycomb lattice (Methods, honeycomb Bloch
+// Hamiltonian): per flavour H(k) = [[Delta - (mu - alpha), eps], [eps*,
+// -Delta - (mu - alpha)]], eps(k) = -t (1 + e^{i k.b1} + e^{i k.b2}).  With
+// H = d0 + d.sigma, |d| = r: f(H) = (f(d0 + r) + f(d0 - r)) / 2 + (f(d0 + r) -
+// f(d0 - r)) / 2 * d.sigma / r, so per k two eigenvalues and the unit vector
+// d / r (in LDS) give every sublattice entry.  One workgroup per
+// configuration; thread per vertex pair, four sublattice entries each.
+// ---------------------------------------------------------------------------
+struct HcParams {
+    double mu[COS_FMAX], alpha[COS_FMAX], delta[COS_FMAX];
+    double t, beta;
+    int L, nmat;
+};
+
+// imaginary-time factor of one eigenvalue x for the time difference d
+__device__ __forceinline__ double g0_branch(double x, double d, double beta) {
+    if (d > 0.0)   // -exp(-x d)(1 - nF), every exponent kept non-positive
+        return (x >= 0.0) ? -exp(-x * d) / (1.0 + exp(-beta * x)) : -exp(x * (beta - d)) / (exp(beta * x) + 1.0);
+    const double s = -d;   // exp(x s) nF
+    return (x <= 0.0) ? exp(x * s) / (exp(beta * x) + 1.0) : exp(-x * (beta - s)) / (1.0 + exp(-beta * x));
+}
+
+__global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__restrict__ nvec,
+                                                           const int64_t *__restrict__ voff,
+                                                           const int32_t *__restrict__ cells,
+                                                           const double *__restrict__ tau,
+                                                           const int64_t *__restrict__ Goff,
+                                                           double *__restrict__ Gout, const HcParams p) {
+    extern __shared__ double sm[];
+    const int L = p.L, L2 = L * L;
+    double *ep = sm, *em = sm + L2, *rz = sm + 2 * L2, *ex = sm + 3 * L2, *ey = sm + 4 * L2;
+    double *cs = sm + 5 * L2, *sn = cs + L;   // cos / sin (2 pi j / L)
+    const int c = blockIdx.x;
+    const int n = nvec[c];
+    const int64_t v0 = voff[c];
+    const int64_t goff = Goff[c];
+    const int D = 2 * n;
+    for (int j = threadIdx.x; j < L; j += blockDim.x) {
+        cs[j] = cospi(2.0 * (double)j / (double)L);
+        sn[j] = sinpi(2.0 * (double)j / (double)L);
+    }
+    for (int g = 0; g < p.nmat; ++g) {
+        __syncthreads();
+        for (int k = threadIdx.x; k < L2; k += blockDim.x) {
+            const int m1 = k % L, m2 = k / L;
+            const double er = -p.t * (1.0 + cospi(2.0 * m1 / (double)L) + cospi(2.0 * m2 / (double)L));
+            const double ei = -p.t * (sinpi(2.0 * m1 / (double)L) + sinpi(2.0 * m2 / (double)L));
+            const double d0 = -(p.mu[g] - p.alpha[g]), dz = p.delta[g];
+            const double r = sqrt(er * er + ei * ei + dz * dz);
+            ep[k] = d0 + r;
+            em[k] = d0 - r;
+            const double inv = r > 0.0 ? 1.0 / r : 0.0;   // r = 0: both eigenvalues equal, f(H) = f(d0)
+            rz[k] = dz * inv;
+            ex[k] = er * inv;
+            ey[k] = ei * inv;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+            const int a = e / n, b = e % n;
+            const int r1 = cells[2 * (v0 + a)] - cells[2 * (v0 + b)];
+            const int r2 = cells[2 * (v0 + a) + 1] - cells[2 * (v0 + b) + 1];
+            const double d = tau[v0 + a] - tau[v0 + b];
+            double aa = 0.0, bb = 0.0, ab = 0.0, ba = 0.0;
+            for (int k = 0; k < L2; ++k) {
+                const int m1 = k % L, m2 = k / L;
+                int ph = (m1 * r1 + m2 * r2) % L;
+                if (ph < 0) ph += L;
+                const double fp = g0_branch(ep[k], d, p.beta), fm = g0_branch(em[k], d, p.beta);
+                const double S = 0.5 * (fp + fm), Dd = 0.5 * (fp - fm);
+                const double c0 = cs[ph], s0 = sn[ph];
+                aa = __builtin_fma(c0, __builtin_fma(Dd, rz[k], S), aa);
+                bb = __builtin_fma(c0, __builtin_fma(-Dd, rz[k], S), bb);
+                // Re[e^{i phi} Dd (ex + i ey)] and Re[e^{i phi} Dd (ex - i ey)]
+                const double xr = Dd * ex[k], xi = Dd * ey[k];
+                ab = __builtin_fma(c0, xr, __builtin_fma(-s0, xi, ab));
+                ba = __builtin_fma(c0, xr, __builtin_fma(s0, xi, ba));
+            }
+            const double inv = 1.0 / (double)L2;
+            double *out = Gout + goff + (int64_t)g * D * D;
+            out[(2 * a) * D + 2 * b] = aa * inv;
+            out[(2 * a) * D + 2 * b + 1] = ab * inv;
+            out[(2 * a + 1) * D + 2 * b] = ba * inv;
+            out[(2 * a + 1) * D + 2 * b + 1] = bb * inv;
+        }
+    }
+}
+
+hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff, const int32_t *cells,
+                               const double *tau, int L, double t, double beta, int nmat, const double *mu,
+                               const double *alpha, const double *delta, const int64_t *Goff, double *G,
+                               hipStream_t s) {
+    HcParams p;
+    for (int g = 0; g < COS_FMAX; ++g) {
+        p.mu[g] = g < nmat ? mu[g] : 0.0;
+        p.alpha[g] = g < nmat ? alpha[g] : 0.0;
+        p.delta[g] = g < nmat ? delta[g] : 0.0;
+    }
+    p.t = t; p.beta = beta; p.L = L; p.nmat = nmat;
+    const size_t shm = (size_t)(5 * L * L + 2 * L) * sizeof(double);
+    hipLaunchKernelGGL(g0_honeycomb_kernel, dim3(nconf), dim3(256), shm, s, n, voff, cells, tau, Goff, G, p);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // chain rule to mu and the shift, one thread per (configuration, matrix)
 // ---------------------------------------------------------------------------
 __global__ void chain_kernel(int nconf, const int32_t *__restrict__ nvec, int nmat,

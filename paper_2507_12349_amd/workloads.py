@@ -3,7 +3,8 @@
 Stand-ins for the Monte Carlo samples of the paper's 32x32-lattice runs
 (Results, honeycomb SU(2) and square-lattice SU(3) studies): vertex sites are
 drawn uniformly over the L x L periodic lattice (with replacement) and
-imaginary times uniformly in [0, beta).  The five workloads below are the
+imaginary times uniformly in [0, beta) (honeycomb: a site is a unit cell,
+its sublattice is summed over by the method).  The workloads below are the
 shapes the library is tested and measured on.  Both the GPU path and the CPU
 oracle take their inputs from here; neither builds propagators here.
 
@@ -37,6 +38,8 @@ class Workload:
     shift_range: tuple = ()      # (lo, hi) for per-flavour shifts delta
     U: float = 1.0               # interaction strength: stub weight = delta / U
     note: str = field(default="", compare=False)
+    lattice: str = "square"      # "honeycomb": sites are unit cells, the sublattice is summed
+    stagger: tuple = ()          # honeycomb: per-flavour staggered field Delta
 
 
 WORKLOADS = {
@@ -53,6 +56,10 @@ WORKLOADS = {
                        mu=(0.0,) * 6, n=0, nconf=8192, seed=4, stubs=True,
                        n_range=(6, 12), shift_range=(-0.2, 0.2), U=1.0,
                        note="16x16, beta=5, SU(6), shifts U[-0.2,0.2], n~U{6..12}, 8192 configs"),
+    "honeycomb": Workload("honeycomb", L=16, t=1.0, beta=5.0, nflav=2, variant=FLAVOUR,
+                          mu=(0.3, 0.3), n=8, nconf=1024, seed=6, lattice="honeycomb", stagger=(0.3, -0.3),
+                          note="16x16 honeycomb cells, beta=5, SU(2) with staggered field +-0.3 per spin, "
+                               "mu=0.3, n=8, 1024 configs, sublattice labels summed"),
     "adjoint": Workload("adjoint", L=8, t=1.0, beta=4.0, nflav=4, variant=UNIFORM,
                         mu=(-0.5,) * 4, n=10, nconf=2048, seed=5, stubs=True,
                         note="8x8, beta=4, SU(4) uniform, mu=-0.5, n=10, 2048 configs, "

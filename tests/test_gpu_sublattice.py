@@ -118,3 +118,49 @@ def test_autotune_and_unsupported_reverse():
         b.adjoint(G, None, None, -1.0, torch.ones_like(out), out, torch.empty_like(G), None)
     assert e.value.status == -5
     b.close()
+
+
+def test_honeycomb_workload(oracle_mod):
+    """The honeycomb workload (1024 configurations of n = 8 on a 16 x 16 cell
+    honeycomb, two flavours with a staggered field), autotuned as bench.py
+    runs it: GPU propagators against the oracle's for sampled configurations,
+    and the labelled connected sums against the oracle's sum over label
+    assignments."""
+    import torch
+    from oracle import g0_honeycomb as GH
+    from oracle import sublattice as SL
+    from paper_2507_12349_amd import _binding as B
+    from paper_2507_12349_amd.workloads import draw
+    announce("honeycomb workload 1024 x n=8, autotuned")
+    d = draw("honeycomb")
+    w = d.workload
+    dev = torch.device("cuda:0")
+    n = d.n.astype(np.int64)
+    sizes = w.nflav * (2 * n) ** 2
+    off = np.zeros(n.size, dtype=np.int64)
+    off[1:] = np.cumsum(sizes[:-1])
+    G = torch.empty(int(sizes.sum()), dtype=torch.float64, device=dev)
+    Goff = torch.as_tensor(off, device=dev)
+    B.build_g0_honeycomb(n.size, torch.as_tensor(d.n, device=dev), torch.as_tensor(d.voff, device=dev),
+                         torch.as_tensor(d.sites, device=dev), torch.as_tensor(d.tau, device=dev), w.L, w.t, w.beta,
+                         np.array(w.mu), np.zeros(w.nflav), np.array(w.stagger), Goff, G)
+    b = B.Batch(d.n, w.nflav, 1, sublattice=True)
+    S = torch.full((n.size,), float("nan"), dtype=torch.float64, device=dev)
+    b.autotune(G, Goff, None, -1.0, S)
+    S.fill_(float("nan"))
+    b.forward(G, Goff, None, -1.0, S)
+    torch.cuda.synchronize()
+    S = S.cpu().numpy()
+    Gh = G.cpu().numpy()
+    assert np.all(np.isfinite(S))
+    b.close()
+    rng = np.random.default_rng(66)
+    for c in sorted(rng.choice(n.size, size=2, replace=False).tolist()):
+        cells, tau = d.config(c)
+        Go = GH.build_g0(w.L, w.t, w.beta, np.array(w.mu), np.zeros(w.nflav), np.array(w.stagger), cells, tau)
+        Gg = Gh[off[c]:off[c] + sizes[c]].reshape(Go.shape)
+        assert np.allclose(Gg, Go, rtol=1e-12, atol=1e-14), c
+        # the sum itself on the propagators the GPU used (compared above)
+        ref = SL.by_assignment(Gg, w.nflav, 1)
+        sabs = SL.by_assignment(np.abs(Gg), w.nflav, 1, 1.0)
+        assert abs(S[c] - ref) <= 8 * 8 * 10 * EPS * sabs, (c, S[c], ref, sabs)
