@@ -54,6 +54,62 @@ def _traffic(kernel):
     return None if e is None else e.get("bytes_per_launch")
 
 
+def honeycomb_forward(B, torch, reps):
+    """Second workload (bipartite lattice, sublattice labels summed): honeycomb
+    propagators + labelled forward levels over 1024 configurations of n = 8,
+    two flavours; inputs resident on the device, launch shape autotuned."""
+    from paper_2507_12349_amd.workloads import draw
+    d = draw("honeycomb")
+    w = d.workload
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    n = d.n.astype(np.int64)
+    sizes = w.nflav * (2 * n) ** 2
+    off = np.zeros(n.size, dtype=np.int64)
+    off[1:] = np.cumsum(sizes[:-1])
+    G = torch.empty(int(sizes.sum()), dtype=torch.float64, device=dev)
+    Goff = torch.as_tensor(off, device=dev)
+    dn, dv = torch.as_tensor(d.n, device=dev), torch.as_tensor(d.voff, device=dev)
+    dc, dt = torch.as_tensor(d.sites, device=dev), torch.as_tensor(d.tau, device=dev)
+    mu, al, st = np.array(w.mu), np.zeros(w.nflav), np.array(w.stagger)
+    b = B.Batch(d.n, w.nflav, 1, sublattice=True)
+    S = torch.empty(n.size, dtype=torch.float64, device=dev)
+
+    def g0():
+        B.build_g0_honeycomb(n.size, dn, dv, dc, dt, w.L, w.t, w.beta, mu, al, st, Goff, G, stream)
+
+    g0()
+    b.autotune(G, Goff, None, -1.0, S, stream=stream)
+    b.forward(G, Goff, None, -1.0, S, stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    b.timing(True)
+    e0.record(stream)
+    for _ in range(reps):
+        g0()
+        b.forward(G, Goff, None, -1.0, S, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ph, _ = b.timing_read()
+    b.timing(False)
+    ms = e0.elapsed_time(e1) / reps
+    fwd_ms = ph["forward"] / reps
+    nn = int(n[0])
+    pc = B.plan_counts_sublattice(nn)
+    flop = w.nflav * 2.0 * (pc["ext"] + pc["closes"])          # per configuration
+    states_bytes = w.nflav * 16.0 * pc["states"]                # each state written once, read once
+    shape = b.launch_shape(nn)
+    b.close()
+    return {"workload": "honeycomb: 16x16 cells, beta=5, SU(2) flavour-dependent (staggered field +-0.3), "
+                        "mu=0.3, n=8, %d configs, sublattice labels summed (2n x 2n matrices)" % n.size,
+            "configs_per_s": n.size / (ms * 1e-3), "ms_per_batch_incl_g0": ms, "forward_levels_ms": fwd_ms,
+            "kernel": "sub_fwd_kernel<8,true>", "launch_shape": shape,
+            "flop_per_config": flop, "forward_tflops": flop * n.size / (fwd_ms * 1e-3) / 1e12,
+            "frac_of_fp64_peak": flop * n.size / (fwd_ms * 1e-3) / PEAK_FP64,
+            "state_stream_bytes_per_config": states_bytes,
+            "state_stream_TBps": states_bytes * n.size / (fwd_ms * 1e-3) / 1e12}
+
+
 def cpu_baseline(d, nsample, threads):
     """The oracle (C, float64) on host cores: propagators (numpy), reverse sweep
     with the forward sum (oracle DP), chain rule; one configuration per task."""
@@ -87,6 +143,7 @@ def main():
     ap.add_argument("--nconf", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of autotuned ones")
+    ap.add_argument("--no-honeycomb", action="store_true", help="skip the sublattice (honeycomb) measurement")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
@@ -134,6 +191,9 @@ def main():
         fwd_batch.forward(G, geo.Goff, None, -1.0, S, stream)
         batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
         torch.cuda.synchronize()
+        if not args.no_honeycomb:
+            honeycomb_forward(B, torch, 1)
+            torch.cuda.synchronize()
         print(json.dumps({"counters_pass": "done", "copy_bytes": 2 * 8 * (1 << 27)}), flush=True)
         return
 
@@ -258,6 +318,8 @@ def main():
                "ai_flop_per_byte": ai,
                "frac_of_attainable": achieved / min(PEAK_FP64, ai * PEAK_HBM)}
 
+    hc = None if args.no_honeycomb else honeycomb_forward(B, torch, max(3, args.steps // 2))
+
     cpu = None
     if not args.no_cpu:
         threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
@@ -301,6 +363,7 @@ def main():
                      "flop_per_launch": flop_launch, "avg_launch_ms": launch_ms,
                      "flop_per_config_sweep": flop_rev, "hbm": hbm,
                      "forward_kernel_tflops": flop_fwd * nconf / (phases["forward"] / args.steps * 1e-3) / 1e12},
+        "sublattice_honeycomb_forward": hc,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)

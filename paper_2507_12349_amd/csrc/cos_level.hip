@@ -108,9 +108,10 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
     // the row instead of hoisted into N^2 registers for the whole loop
     asm volatile("" : "+v"(gaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
-    // only current slots are loaded (the row's dense product is cheaper than
-    // skipping the zero rows of f: measured)
-    double f[N], acc[N];
+    // only current slots are loaded; the product f . G is formed output by
+    // output, and only for the outputs the row uses (open vertices and the
+    // head's close): each is consumed at once, no array crosses a branch
+    double f[N];
 #pragma unroll
     for (int v = 0; v < N; ++v) {
         const bool c = (cm >> v) & 1u;
@@ -121,20 +122,16 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
         for (int v = 0; v < N; ++v) f[v] = v == 0 ? 1.0 : 0.0;
     }
 #pragma unroll
-    for (int w = 0; w < N; ++w) acc[w] = 0.0;
-#pragma unroll
-    for (int v = 0; v < N; ++v)
-#pragma unroll
-        for (int w = 0; w < N; ++w) acc[w] = __builtin_fma(f[v], Gs[(v * N + w) * 64], acc[w]);
-#pragma unroll
-    for (int w = 0; w < N; ++w)
-        if (w == u) cp += acc[w];
-#pragma unroll
     for (int w = 0; w < N; ++w) {
         const uint32_t bit = 1u << w;
+        if ((twos & bit) && w != u) continue;   // wave-uniform: output not needed
+        double a = 0.0;
+#pragma unroll
+        for (int v = 0; v < N; ++v) a = __builtin_fma(f[v], Gs[(v * N + w) * 64], a);
+        if (w == u) cp += a;
         if (twos & bit) continue;
         const bool first = !(ones & bit);
-        double val = first ? 2.0 * acc[w] : acc[w];
+        double val = first ? 2.0 * a : a;
         if (!first && (cm & bit)) val = __builtin_fma(-sgx, f[w], val);
         if (w == 0 && u == 0 && !(twos & 1u)) {
             dext = val;   // m_0 = 1: the next cycle opens on this same slot

@@ -8,7 +8,8 @@
 // current flavour sits in LDS as [2n][2n][lane] ((2n)^2 x 512 B, 128 KB at
 // n = 8), shared by the 16 wavefronts of a workgroup.
 //
-// Rules per row (m, u, s_u), current slots f[(v, s_v)], acc = f . G:
+// Rules per row (m, u, s_u), current slots f[(v, s_v)], acc = f . G (formed
+// output by output, only for the outputs the row uses):
 //   a once-unvisited w is reached on either label: child (m + (w, s)), slot
 //   (w, s) = 2 acc[(w, s)] (first visit: either point of w);
 //   a once-visited w keeps its label s: child (m with w twice), slot (w, s) =
@@ -62,7 +63,7 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
     const double *__restrict__ src = cur + lam * cpl + (int64_t)r * D * 64;
     asm volatile("" : "+v"(gaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
-    double f[D], acc[D];
+    double f[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) f[i] = ((cs >> i) & 1u) ? lane_ld(src + i * 64, lane8) : 0.0;
     if (start) {
@@ -70,29 +71,27 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
         for (int i = 0; i < D; ++i) f[i] = i == su ? 1.0 : 0.0;   // start: vertex 0 on label s_u
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j) acc[j] = 0.0;
-#pragma unroll
-    for (int i = 0; i < D; ++i)
-#pragma unroll
-        for (int j = 0; j < D; ++j) acc[j] = __builtin_fma(f[i], Gs[(i * D + j) * 64], acc[j]);
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-        if (j == 2 * u + su) cp += acc[j];
-#pragma unroll
     for (int w = 0; w < N; ++w) {
         const uint32_t bit = 1u << w;
-        if (twos & bit) continue;
-        if (!(ones & bit)) {
-            // first visit, on either label; the child's heads are the parent's
-            const int hs = sub_head_slot(u, su, twos);
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int crow = M.crb[2 * w + s] + hs;
-                lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * w + s) * 64, lane8, 2.0 * acc[2 * w + s]);
+        for (int s = 0; s < 2; ++s) {
+            const int j = 2 * w + s;
+            const bool close = (w == u) && (s == su);
+            // outputs used: both labels of an unvisited w, the kept label of a
+            // once-visited w, and the close slot (wave-uniform tests)
+            const bool ext = !(twos & bit) && (!(ones & bit) || (int)((subb >> w) & 1u) == s);
+            if (!ext && !close) continue;
+            double a = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) a = __builtin_fma(f[i], Gs[(i * D + j) * 64], a);
+            if (close) cp += a;
+            if (!ext) continue;
+            if (!(ones & bit)) {
+                const int crow = M.crb[j] + sub_head_slot(u, su, twos);
+                lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + j * 64, lane8, 2.0 * a);
+                continue;
             }
-        } else {
-            const int s = (subb >> w) & 1u;
-            const double val = s ? acc[2 * w + 1] : acc[2 * w];
+            const double val = a;
             if (w == 0 && u == 0) {
                 dext = val;   // vertex 0 once visited: the next cycle opens on this same slot
                 continue;
