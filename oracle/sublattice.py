@@ -18,6 +18,8 @@ Argument convention: ``A`` has shape (2n, 2n) (variant U) or (nf, 2n, 2n)
                           (oracle O3 per assignment)
   :func:`brute_labeled`   independent enumeration of labelled permutations
                           (pure Python, n <= 3)
+  :func:`alg1_brute`      the SU(2) form of Alg. 1 (up and down point per
+                          vertex, cycles inside a block) by enumeration
   :func:`plan_counts`     breadth-first enumeration of the labelled DP states
 """
 from __future__ import annotations
@@ -97,6 +99,46 @@ def brute_labeled(A, nf: int, variant: int = 0, w: float = -1.0) -> float:
                     csum += prod
                 term *= w * (nf * csum if variant == 0 else csum)
             total += term
+    return total
+
+
+def alg1_brute(A_up, A_dn, w: float = -1.0) -> float:
+    """SU(2) bipartite sum as Alg. 1 states it, by enumeration (tiny n): the 2n
+    points are the up point k and the down point k + n of each vertex k; a
+    cycle stays inside one block (Blk: up points go to up points); labels s_k
+    are summed; a cycle contributes w * prod A_block[2 v(p) + s][2 v(pi p) + t];
+    only connected diagrams count."""
+    A_up = np.asarray(A_up, dtype=np.float64)
+    A_dn = np.asarray(A_dn, dtype=np.float64)
+    n = A_up.shape[-1] // 2
+    total = 0.0
+    for s in itertools.product((0, 1), repeat=n):
+        lab = [2 * k + s[k] for k in range(n)]
+        for pu in itertools.permutations(range(n)):
+            for pd in itertools.permutations(range(n)):
+                parent = list(range(n))
+
+                def find(x):
+                    while parent[x] != x:
+                        parent[x] = parent[parent[x]]
+                        x = parent[x]
+                    return x
+                term = 1.0
+                for perm, M in ((pu, A_up), (pd, A_dn)):
+                    seen = [False] * n
+                    for k0 in range(n):
+                        if seen[k0]:
+                            continue
+                        prod = 1.0
+                        k = k0
+                        while not seen[k]:
+                            seen[k] = True
+                            prod *= M[lab[k], lab[perm[k]]]
+                            parent[find(perm[k])] = find(k)
+                            k = perm[k]
+                        term *= w * prod
+                if len({find(k) for k in range(n)}) == 1:
+                    total += term
     return total
 
 

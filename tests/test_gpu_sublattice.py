@@ -164,3 +164,17 @@ def test_honeycomb_workload(oracle_mod):
         ref = SL.by_assignment(Gg, w.nflav, 1)
         sabs = SL.by_assignment(np.abs(Gg), w.nflav, 1, 1.0)
         assert abs(S[c] - ref) <= 8 * 8 * 10 * EPS * sabs, (c, S[c], ref, sabs)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_alg1_su2_block_form(n):
+    """Alg. 1 (SU(2): one up and one down point per vertex, cycles inside a
+    block) is the two-flavour labelled sum divided by 2^n."""
+    from oracle import sublattice as SL
+    announce("sublattice: Alg. 1 SU(2) block form n=%d" % n)
+    rng = np.random.default_rng(950 + n)
+    A = rng.normal(size=(2, 2 * n, 2 * n)) * 0.6
+    S, _ = _run([A], 2, 1)
+    ref = SL.alg1_brute(A[0], A[1])
+    sabs = SL.by_assignment(np.abs(A), 2, 1, 1.0) / 2 ** n
+    assert abs(S[0] / 2 ** n - ref) <= 8 * n * (n + 2) * EPS * sabs, (S[0] / 2 ** n, ref)

@@ -64,3 +64,16 @@ def test_state_space(n):
     assert c["closes"] == c["states"]
     # each state of level l < 2n extends to one child per (open vertex, admissible label)
     assert c["ext"] > c["states"] or n == 1
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_alg1_is_two_flavour_sum_over_2n(oracle_mod, n):
+    """Alg. 1 (SU(2), one up and one down point per vertex, cycles inside a
+    block) equals the two-flavour sum divided by 2^n: in the flavour sum a
+    vertex with both points in one flavour cancels (equal rows), and each
+    vertex with one point per flavour appears twice (which point is up)."""
+    rng = np.random.default_rng(900 + n)
+    A = _rand(rng, n, 2)
+    got = SL.alg1_brute(A[0], A[1])
+    ref = SL.by_assignment(A, 2, 1) / 2 ** n
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (got, ref)
