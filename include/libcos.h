@@ -209,6 +209,29 @@ cos_status cos_batch_timing_read(cos_batch_t b, double *ms, int32_t *ncalls);
 cos_status cos_plan_counts_sublattice(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
                                       int64_t *masks, int64_t *rows);
 
+/* Monte Carlo support (the series coefficients are integrals of the
+ * connected sum over vertex sites and times; Methods, diagrammatic
+ * expansion).  cos_mc_sample writes nconf configurations of order n for the
+ * G0 builders: vertex 0 at site (0, 0) and time 0 (translation invariance),
+ * vertices 1..n-1 uniform over the L x L sites and [0, beta), drawn from a
+ * counter-based generator: the splitmix64 output function (Steele, Lea,
+ * Flood 2014) of seed + 0x9E3779B97F4A7C15 * (ctr + 1), with ctr =
+ * ((first + c) * n + k) * 2 + q for component q (0 site, 1 time) of vertex k
+ * of configuration c; site = ((z >> 32) * L^2) >> 32 as x + L y, time =
+ * beta * (z >> 11) * 2^-53.  d_sites int32 [nconf*n][2], d_tau [nconf*n]
+ * (configurations back to back).  Asynchronous on `stream`. */
+cos_status cos_mc_sample(int32_t nconf, int32_t n, int32_t L, double beta, uint64_t seed, int64_t first,
+                         int32_t *d_sites, double *d_tau, void *stream);
+/* d_acc[0] += sum_i d_x[i], d_acc[1] += sum_i d_x[i]^2 over count values
+ * (device buffers, fixed summation order).  Asynchronous on `stream`. */
+cos_status cos_accumulate_moments(int32_t count, const double *d_x, double *d_acc, void *stream);
+/* [m/k] Pade approximant of sum_{i=0}^{m+k} a_i x^i evaluated at x (HOST
+ * arrays; Results, Pade re-summation): *value, and when grad is not NULL
+ * grad[i] = d value / d a_i for i = 0..m+k (for the linear error propagation
+ * delta^2 = sum_i grad_i^2 delta_a_i^2).  COS_ERANGE when the approximant
+ * does not exist (singular denominator system). */
+cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *value, double *grad);
+
 /* Diagnostics. */
 const char *cos_status_string(cos_status s);
 const char *cos_last_error(void);

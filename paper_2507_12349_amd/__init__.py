@@ -7,7 +7,8 @@ The work runs in hand-written HIP kernels for gfx950 behind the C ABI of
 first use: touching any of them without the built library raises ImportError
 (there is no CPU fallback).  ``workloads`` (seeded inputs) needs no library.
 """
-_BINDING = {"Batch", "CosError", "connected_sum_host", "plan_counts", "plan_counts_sublattice", "build_g0", "build_g0_honeycomb",
+_BINDING = {"Batch", "CosError", "connected_sum_host", "plan_counts", "plan_counts_sublattice", "build_g0", "build_g0_honeycomb", "mc_sample",
+            "accumulate_moments", "pade",
             "chain_mu_shift", "UNIFORM", "FLAVOUR", "F_STUBS", "F_SUBLATTICE", "NMAX", "FMAX", "NMAX_SUBLATTICE",
             "LIB_PATH", "EXPORTED", "lib"}
 

@@ -24,7 +24,7 @@ EXPORTED = (
     "cos_connected_sum_adjoint", "cos_connected_sum", "cos_build_g0", "cos_chain_mu_shift",
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
-    "cos_plan_counts_sublattice", "cos_build_g0_honeycomb",
+    "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -51,6 +51,9 @@ def _load():
         "cos_plan_counts": ([i32, P64, P64, P64, P64, P64, P64], i32),
         "cos_plan_counts_sublattice": ([i32, P64, P64, P64, P64, P64], i32),
         "cos_build_g0_honeycomb": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p], i32),
+        "cos_mc_sample": ([i32, i32, i32, d, ctypes.c_uint64, i64, p, p, p], i32),
+        "cos_accumulate_moments": ([i32, p, p, p], i32),
+        "cos_pade": ([i32, i32, p, d, ctypes.POINTER(d), p], i32),
         "cos_status_string": ([i32], ctypes.c_char_p),
         "cos_last_error": ([], ctypes.c_char_p),
         "cos_release": ([], i32),
@@ -216,6 +219,28 @@ def build_g0_honeycomb(nconf, n, voff, cells, tau, L, t, beta, mu, alpha, delta,
     _check(lib.cos_build_g0_honeycomb(int(nconf), _ptr(n), _ptr(voff), _ptr(cells), _ptr(tau), int(L), float(t),
                                       float(beta), int(mu.size), _ptr(mu), _ptr(alpha), _ptr(delta), _ptr(Goff),
                                       _ptr(G), _stream(stream)), "cos_build_g0_honeycomb")
+
+
+def mc_sample(nconf, n, L, beta, seed, first, sites, tau, stream=None):
+    """Device sampler of vertex configurations (vertex 0 at the origin)."""
+    _check(lib.cos_mc_sample(int(nconf), int(n), int(L), float(beta), int(seed) & 0xFFFFFFFFFFFFFFFF, int(first),
+                             _ptr(sites), _ptr(tau), _stream(stream)), "cos_mc_sample")
+
+
+def accumulate_moments(count, x, acc, stream=None):
+    """acc[0] += sum x, acc[1] += sum x^2 (device)."""
+    _check(lib.cos_accumulate_moments(int(count), _ptr(x), _ptr(acc), _stream(stream)), "cos_accumulate_moments")
+
+
+def pade(a, m: int, k: int, x: float = 1.0):
+    """[m/k] Pade approximant of sum_i a_i x^i at x and its gradient in a (host)."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(-1))
+    if a.size < m + k + 1:
+        raise ValueError("need %d coefficients for [%d/%d]" % (m + k + 1, m, k))
+    v = ctypes.c_double()
+    g = np.zeros(m + k + 1)
+    _check(lib.cos_pade(int(m), int(k), _ptr(a), float(x), ctypes.byref(v), _ptr(g)), "cos_pade")
+    return v.value, g
 
 
 def chain_mu_shift(nconf, n, nmat, Goff, G_bar, dG, stub_bar, nstub, U, mu_bar, alpha_bar, stream=None):

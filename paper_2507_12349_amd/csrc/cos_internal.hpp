@@ -158,6 +158,10 @@ hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff,
                                const double *tau, int L, double t, double beta, int nmat, const double *mu,
                                const double *alpha, const double *delta, const int64_t *Goff, double *G,
                                hipStream_t s);
+// Monte Carlo support (cos_mc.hip)
+hipError_t launch_mc_sample(int nconf, int n, int L, double beta, uint64_t seed, int64_t first, int32_t *sites,
+                            double *tau, hipStream_t s);
+hipError_t launch_moments(int count, const double *x, double *acc, hipStream_t s);
 hipError_t launch_chain(int nconf, const int32_t *n, int nmat, const int64_t *Goff, const double *Gb,
                         const double *dG, const double *sb, int nstub, double U, double *mub,
                         double *alb, hipStream_t s);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
+#include <complex>
 #include <cstring>
 #include <functional>
 #include <map>
@@ -913,6 +914,101 @@ cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat, c
     if (d_stub_bar && U == 0.0) return fail(COS_EINVAL, "U must be nonzero");
     HIP_TRY(launch_chain(nconf, d_n, nmat, d_Goff, d_G_bar, d_dG, d_stub_bar, nstub, U, d_mu_bar, d_alpha_bar,
                          (hipStream_t)stream));
+    return COS_OK;
+}
+
+cos_status cos_mc_sample(int32_t nconf, int32_t n, int32_t L, double beta, uint64_t seed, int64_t first,
+                         int32_t *d_sites, double *d_tau, void *stream) {
+    if (nconf < 1 || !d_sites || !d_tau) return fail(COS_EINVAL, "nconf >= 1 and output buffers are required");
+    if (n < 1 || n > COS_NMAX) return fail(COS_ERANGE, "n must be in [1, %d], got %d", COS_NMAX, n);
+    if (L < 1 || L > 32) return fail(COS_ERANGE, "L must be in [1, 32], got %d", L);
+    if (!(beta > 0.0)) return fail(COS_ERANGE, "beta must be positive");
+    if (first < 0) return fail(COS_EINVAL, "first must be >= 0");
+    HIP_TRY(launch_mc_sample(nconf, n, L, beta, seed, first, d_sites, d_tau, (hipStream_t)stream));
+    return COS_OK;
+}
+
+cos_status cos_accumulate_moments(int32_t count, const double *d_x, double *d_acc, void *stream) {
+    if (count < 1 || !d_x || !d_acc) return fail(COS_EINVAL, "count >= 1 and device buffers are required");
+    HIP_TRY(launch_moments(count, d_x, d_acc, (hipStream_t)stream));
+    return COS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// value of the [m/k] Pade approximant of sum_i a_i x^i at x (T = double, or
+// complex for the complex-step derivative); false when the denominator system
+// is singular
+template <class T>
+bool pade_eval(int m, int k, const T *a, double x, T *value) {
+    // denominator q_0 = 1, q_1..q_k: sum_{j=0..k} q_j a_{i-j} = 0 for i = m+1..m+k
+    std::vector<T> A((size_t)k * k), rhs(k), q(k + 1);
+    for (int r = 0; r < k; ++r) {
+        const int i = m + 1 + r;
+        for (int j = 1; j <= k; ++j) A[(size_t)r * k + (j - 1)] = (i - j >= 0) ? a[i - j] : T(0.0);
+        rhs[r] = -a[i];
+    }
+    // Gaussian elimination with partial pivoting
+    for (int c = 0; c < k; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < k; ++r)
+            if (std::abs(A[(size_t)r * k + c]) > std::abs(A[(size_t)piv * k + c])) piv = r;
+        if (std::abs(A[(size_t)piv * k + c]) == 0.0) return false;
+        if (piv != c) {
+            for (int j = 0; j < k; ++j) std::swap(A[(size_t)c * k + j], A[(size_t)piv * k + j]);
+            std::swap(rhs[c], rhs[piv]);
+        }
+        for (int r = c + 1; r < k; ++r) {
+            const T f = A[(size_t)r * k + c] / A[(size_t)c * k + c];
+            for (int j = c; j < k; ++j) A[(size_t)r * k + j] -= f * A[(size_t)c * k + j];
+            rhs[r] -= f * rhs[c];
+        }
+    }
+    q[0] = T(1.0);
+    for (int c = k - 1; c >= 0; --c) {
+        T v = rhs[c];
+        for (int j = c + 1; j < k; ++j) v -= A[(size_t)c * k + j] * q[j + 1];
+        q[c + 1] = v / A[(size_t)c * k + c];
+    }
+    // numerator p_i = sum_{j<=min(i,k)} q_j a_{i-j}; Horner in x
+    T P(0.0), Q(0.0);
+    for (int i = m; i >= 0; --i) {
+        T pi(0.0);
+        for (int j = 0; j <= std::min(i, k); ++j) pi += q[j] * a[i - j];
+        P = P * x + pi;
+    }
+    for (int j = k; j >= 0; --j) Q = Q * x + q[j];
+    if (std::abs(Q) == 0.0) return false;
+    *value = P / Q;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *value, double *grad) {
+    if (!a || !value) return fail(COS_EINVAL, "a and value are required");
+    if (m < 0 || k < 0 || m + k > 64) return fail(COS_ERANGE, "need 0 <= m, k and m + k <= 64");
+    const int na = m + k + 1;
+    double v = 0.0;
+    if (!pade_eval<double>(m, k, a, x, &v)) return fail(COS_ERANGE, "the [%d/%d] approximant does not exist", m, k);
+    *value = v;
+    if (grad) {
+        // complex-step derivative: d value / d a_j = Im value(a + i h e_j) / h, exact to rounding
+        const double h = 1e-30;
+        std::vector<std::complex<double>> ac(a, a + na);
+        for (int j = 0; j < na; ++j) {
+            ac[j] += std::complex<double>(0.0, h);
+            std::complex<double> vc;
+            if (!pade_eval<std::complex<double>>(m, k, ac.data(), x, &vc))
+                return fail(COS_ERANGE, "the [%d/%d] approximant does not exist", m, k);
+            grad[j] = vc.imag() / h;
+            ac[j] = a[j];
+        }
+    }
     return COS_OK;
 }
 
