@@ -110,6 +110,38 @@ def honeycomb_forward(B, torch, reps):
             "state_stream_TBps": states_bytes * n.size / (fwd_ms * 1e-3) / 1e12}
 
 
+def mc_series(torch, orders=8, nconf=8192, nbatches=4):
+    """Monte Carlo series of the interaction correction to ln Z per site and
+    unit time on the adjoint workload's lattice (8x8, beta=4, mu=-0.5, SU(4),
+    U=1) through the device driver, and its Pade band ([m/m], m = 1..4, at
+    xi = 1).  Reports the sampling rate at the highest order."""
+    from paper_2507_12349_amd import mc
+    kw = dict(L=8, t=1.0, beta=4.0, mu=[-0.5], alpha=[0.0], nflav=4, variant=0, U=1.0, nconf=nconf,
+              nbatches=nbatches)
+    coefs, top_ms = [], None
+    for n in range(1, orders + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        c = mc.lnz_coefficient(n, seed=2024 + n, **kw)
+        e1.record()
+        torch.cuda.synchronize()
+        coefs.append(c)
+        top_ms = e0.elapsed_time(e1)
+    a = np.array([0.0] + [c.value for c in coefs])
+    da = np.array([0.0] + [c.error for c in coefs])
+    degrees = [m for m in (1, 2, 3, 4) if 2 * m <= orders]
+    try:
+        lo, hi, vals, errs = mc.pade_band(a, da, degrees)
+        pade = {"degrees": degrees, "values": vals, "errors": errs, "band": [lo, hi]}
+    except Exception as exc:   # an approximant may not exist for a given series
+        pade = {"error": str(exc)}
+    return {"workload": "8x8 square lattice, beta=4, mu=-0.5, SU(4) uniform, U=1; vertex 0 fixed, %d x %d "
+                        "samples per order" % (nbatches, nconf),
+            "coefficients": [{"n": c.n, "value": c.value, "error": c.error} for c in coefs],
+            "samples_per_s_at_top_order": nconf * nbatches / (top_ms * 1e-3),
+            "pade_of_correction_at_xi_1": pade}
+
+
 def cpu_baseline(d, nsample, threads):
     """The oracle (C, float64) on host cores: propagators (numpy), reverse sweep
     with the forward sum (oracle DP), chain rule; one configuration per task."""
@@ -144,6 +176,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of autotuned ones")
     ap.add_argument("--no-honeycomb", action="store_true", help="skip the sublattice (honeycomb) measurement")
+    ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo series measurement")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
@@ -319,6 +352,7 @@ def main():
                "frac_of_attainable": achieved / min(PEAK_FP64, ai * PEAK_HBM)}
 
     hc = None if args.no_honeycomb else honeycomb_forward(B, torch, max(3, args.steps // 2))
+    mcs = None if args.no_mc else mc_series(torch)
 
     cpu = None
     if not args.no_cpu:
@@ -364,6 +398,7 @@ def main():
                      "flop_per_config_sweep": flop_rev, "hbm": hbm,
                      "forward_kernel_tflops": flop_fwd * nconf / (phases["forward"] / args.steps * 1e-3) / 1e12},
         "sublattice_honeycomb_forward": hc,
+        "mc_series": mcs,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
