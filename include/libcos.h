@@ -232,6 +232,23 @@ cos_status cos_accumulate_moments(int32_t count, const double *d_x, double *d_ac
  * does not exist (singular denominator system). */
 cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *value, double *grad);
 
+/* CDet comparison path (Methods: the 3^n labelled principal minors by
+ * Schur complements with pseudo-pivots, then the connected part by the
+ * subset recursion; the paper's instability study) for the SU(2) bipartite
+ * model.  Per configuration d_A holds two 2n x 2n matrices, spin up then
+ * spin down, index 2k + s as for COS_F_SUBLATTICE ([nconf][2][2n][2n]).
+ * d_out[c] = sum over the 2^n full labellings of the connected part of
+ * det A_up[T] det A_dn[T] (the quantity of Alg. 1, which equals the
+ * two-flavour COS_F_SUBLATTICE sum divided by 2^n).  precision 0: FP64;
+ * 1: double-double (software, about 32 significant digits).  A pivot of
+ * magnitude below eps is replaced by C = sum |A| / (2n)^2 and the affected
+ * minors are corrected afterwards by multilinearity (deepest first).
+ * 1 <= n <= COS_NMAX_SUBLATTICE.  The caller provides d_work of at least
+ * the size cos_cdet_workspace returns.  Asynchronous on `stream`. */
+cos_status cos_cdet_workspace(int32_t n, int32_t nconf, int32_t precision, uint64_t *bytes);
+cos_status cos_cdet_su2(int32_t nconf, int32_t n, const double *d_A, int32_t precision, double eps,
+                        void *d_work, uint64_t work_bytes, double *d_out, void *stream);
+
 /* Diagnostics. */
 const char *cos_status_string(cos_status s);
 const char *cos_last_error(void);

@@ -25,6 +25,7 @@ EXPORTED = (
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
+    "cos_cdet_workspace", "cos_cdet_su2",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -54,6 +55,8 @@ def _load():
         "cos_mc_sample": ([i32, i32, i32, d, ctypes.c_uint64, i64, p, p, p], i32),
         "cos_accumulate_moments": ([i32, p, p, p], i32),
         "cos_pade": ([i32, i32, p, d, ctypes.POINTER(d), p], i32),
+        "cos_cdet_workspace": ([i32, i32, i32, ctypes.POINTER(ctypes.c_uint64)], i32),
+        "cos_cdet_su2": ([i32, i32, p, i32, d, p, ctypes.c_uint64, p, p], i32),
         "cos_status_string": ([i32], ctypes.c_char_p),
         "cos_last_error": ([], ctypes.c_char_p),
         "cos_release": ([], i32),
@@ -241,6 +244,19 @@ def pade(a, m: int, k: int, x: float = 1.0):
     g = np.zeros(m + k + 1)
     _check(lib.cos_pade(int(m), int(k), _ptr(a), float(x), ctypes.byref(v), _ptr(g)), "cos_pade")
     return v.value, g
+
+
+def cdet_su2(A, n: int, precision: int, out, eps: float = 1e-12, stream=None):
+    """CDet path on the device: A is a device tensor [nconf][2][2n][2n];
+    allocates its workspace with torch (plumbing) and writes out[nconf]."""
+    import torch
+    nconf = int(out.numel())
+    nb = ctypes.c_uint64()
+    _check(lib.cos_cdet_workspace(int(n), nconf, int(precision), ctypes.byref(nb)), "cos_cdet_workspace")
+    work = torch.empty(int(nb.value), dtype=torch.uint8, device=out.device)
+    _check(lib.cos_cdet_su2(nconf, int(n), _ptr(A), int(precision), float(eps), _ptr(work), nb.value, _ptr(out),
+                            _stream(stream)), "cos_cdet_su2")
+    return work
 
 
 def chain_mu_shift(nconf, n, nmat, Goff, G_bar, dG, stub_bar, nstub, U, mu_bar, alpha_bar, stream=None):

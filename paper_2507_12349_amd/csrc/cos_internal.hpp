@@ -158,6 +158,11 @@ hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff,
                                const double *tau, int L, double t, double beta, int nmat, const double *mu,
                                const double *alpha, const double *delta, const int64_t *Goff, double *G,
                                hipStream_t s);
+// CDet comparison path (cos_cdet.hip): workspace elements per configuration
+// (doubles for precision 0, double-double pairs for 1) and the launcher
+int64_t cdet_elems_per_config(int n);
+hipError_t launch_cdet(int nconf, int n, const double *A, int precision, double eps, void *work, double *out,
+                       hipStream_t s);
 // Monte Carlo support (cos_mc.hip)
 hipError_t launch_mc_sample(int nconf, int n, int L, double beta, uint64_t seed, int64_t first, int32_t *sites,
                             double *tau, hipStream_t s);

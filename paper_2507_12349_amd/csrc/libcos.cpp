@@ -928,6 +928,28 @@ cos_status cos_mc_sample(int32_t nconf, int32_t n, int32_t L, double beta, uint6
     return COS_OK;
 }
 
+cos_status cos_cdet_workspace(int32_t n, int32_t nconf, int32_t precision, uint64_t *bytes) {
+    if (!bytes) return fail(COS_EINVAL, "bytes is NULL");
+    if (n < 1 || n > COS_NMAX_SUBLATTICE) return fail(COS_ERANGE, "n must be in [1, %d], got %d", COS_NMAX_SUBLATTICE, n);
+    if (nconf < 1) return fail(COS_EINVAL, "nconf must be >= 1");
+    if (precision != 0 && precision != 1) return fail(COS_EINVAL, "precision must be 0 (FP64) or 1 (double-double)");
+    *bytes = (uint64_t)cdet_elems_per_config(n) * (uint64_t)nconf * (precision ? 16u : 8u);
+    return COS_OK;
+}
+
+cos_status cos_cdet_su2(int32_t nconf, int32_t n, const double *d_A, int32_t precision, double eps, void *d_work,
+                        uint64_t work_bytes, double *d_out, void *stream) {
+    uint64_t need = 0;
+    cos_status st = cos_cdet_workspace(n, nconf, precision, &need);
+    if (st) return st;
+    if (!d_A || !d_work || !d_out) return fail(COS_EINVAL, "null pointer argument");
+    if (work_bytes < need) return fail(COS_EINVAL, "workspace too small: %llu bytes, need %llu",
+                                       (unsigned long long)work_bytes, (unsigned long long)need);
+    if (!(eps >= 0.0)) return fail(COS_EINVAL, "eps must be >= 0");
+    HIP_TRY(launch_cdet(nconf, n, d_A, precision, eps, d_work, d_out, (hipStream_t)stream));
+    return COS_OK;
+}
+
 cos_status cos_accumulate_moments(int32_t count, const double *d_x, double *d_acc, void *stream) {
     if (count < 1 || !d_x || !d_acc) return fail(COS_EINVAL, "count >= 1 and device buffers are required");
     HIP_TRY(launch_moments(count, d_x, d_acc, (hipStream_t)stream));
