@@ -101,6 +101,7 @@ def honeycomb_forward(B, torch, reps):
     states_bytes = w.nflav * 16.0 * pc["states"]                # each state written once, read once
     shape = b.launch_shape(nn)
     b.close()
+    cdet = cdet_comparison(B, torch, G, S, n.size, nn, w.nflav, stream)
     return {"workload": "honeycomb: 16x16 cells, beta=5, SU(2) flavour-dependent (staggered field +-0.3), "
                         "mu=0.3, n=8, %d configs, sublattice labels summed (2n x 2n matrices)" % n.size,
             "configs_per_s": n.size / (ms * 1e-3), "ms_per_batch_incl_g0": ms, "forward_levels_ms": fwd_ms,
@@ -108,7 +109,33 @@ def honeycomb_forward(B, torch, reps):
             "flop_per_config": flop, "forward_tflops": flop * n.size / (fwd_ms * 1e-3) / 1e12,
             "frac_of_fp64_peak": flop * n.size / (fwd_ms * 1e-3) / PEAK_FP64,
             "state_stream_bytes_per_config": states_bytes,
-            "state_stream_TBps": states_bytes * n.size / (fwd_ms * 1e-3) / 1e12}
+            "state_stream_TBps": states_bytes * n.size / (fwd_ms * 1e-3) / 1e12,
+            "cdet_comparison": cdet}
+
+
+def cdet_comparison(B, torch, G, S, nconf, n, nflav, stream):
+    """The CDet path (3^n labelled principal minors with pseudo-pivots, then
+    the connected recursion) on the honeycomb propagators the labelled DP just
+    summed, in FP64 and in double-double: rate, and deviation from the DP
+    (whose sum over the 2^n label assignments equals 2^n times CDet's)."""
+    assert nflav == 2
+    A = G.reshape(nconf, 2, 2 * n, 2 * n)
+    cos = S / float(2 ** n)
+    res = {}
+    for prec, name in ((0, "fp64"), (1, "double_double")):
+        out = torch.empty(nconf, dtype=torch.float64, device=G.device)
+        B.cdet_su2(A, n, prec, out, 1e-12, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.cdet_su2(A, n, prec, out, 1e-12, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        rel = ((out - cos).abs() / cos.abs().clamp_min(1e-300)).cpu().numpy()
+        res[name] = {"configs_per_s": nconf / (ms * 1e-3), "ms_per_batch": ms,
+                     "rel_dev_from_dp_median": float(np.median(rel)), "rel_dev_from_dp_max": float(np.max(rel))}
+    return res
 
 
 def mc_series(torch, orders=8, nconf=8192, nbatches=4):

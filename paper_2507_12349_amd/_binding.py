@@ -256,6 +256,8 @@ def cdet_su2(A, n: int, precision: int, out, eps: float = 1e-12, stream=None):
     work = torch.empty(int(nb.value), dtype=torch.uint8, device=out.device)
     _check(lib.cos_cdet_su2(nconf, int(n), _ptr(A), int(precision), float(eps), _ptr(work), nb.value, _ptr(out),
                             _stream(stream)), "cos_cdet_su2")
+    if hasattr(stream, "cuda_stream"):
+        work.record_stream(stream)   # keep the workspace until that stream has used it
     return work
 
 
