@@ -77,7 +77,22 @@ enum { COS_UNIFORM = 0, COS_FLAVOUR = 1 };
  * COS_NMAX_SUBLATTICE; forward sums only (the adjoint and the autotuner's
  * reverse sweep return COS_EUNSUPPORTED); not combinable with COS_F_STUBS
  * (shifts enter through the matrices' diagonals). */
-enum { COS_F_STUBS = 1, COS_F_SUBLATTICE = 2 };
+/* COS_F_MASK_ONLY: the SU(2) mask-only variant (Results, the variant for
+ * cycles without extra factors; Methods, Alg. 1).  The DP works on points
+ * (each vertex k has an up point and a down point, one per spin block) and
+ * tracks only the interaction masks: an extension goes from the current point
+ * to any point of its spin block other than the head, onto an interaction not
+ * yet visited twice (a point may thus be visited twice: these non-physical
+ * clows are kept and cancel through the cycle sign); a closed cycle carries
+ * w and the next one opens on the lowest interaction visited once, at either
+ * end except the current head.  Requires COS_FLAVOUR with nflav = 2 (matrix 0
+ * = the up block, matrix 1 = the down block) and cycle_weight = -1 (the
+ * cancellation needs the fermion sign; other weights return COS_EINVAL);
+ * not combinable with COS_F_STUBS.  The result is the SU(2) connected sum,
+ * 2^-n times the COS_FLAVOUR two-flavour sum of the same matrices.  With
+ * COS_F_SUBLATTICE it is Alg. 1 with its sublattice labels (forward only).
+ * The reverse sweep is available without COS_F_SUBLATTICE. */
+enum { COS_F_STUBS = 1, COS_F_SUBLATTICE = 2, COS_F_MASK_ONLY = 4 };
 
 typedef struct cos_batch_s *cos_batch_t;
 
@@ -208,6 +223,16 @@ cos_status cos_batch_timing_read(cos_batch_t b, double *ms, int32_t *ncalls);
  * per flavour: states, extension transitions, closes, masks, rows. */
 cos_status cos_plan_counts_sublattice(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
                                       int64_t *masks, int64_t *rows);
+
+/* State counts of the mask-only variant (COS_F_MASK_ONLY; Alg. 1), for
+ * order n (1..COS_NMAX, or 1..COS_NMAX_SUBLATTICE with flags =
+ * COS_F_SUBLATTICE; flags may hold nothing else): the slots the level kernels
+ * visit, i.e. the states (head point, current point, mask) reachable from the
+ * start, the extension transitions out of them, and the states that close a
+ * cycle (a once-visited interaction exists, or the mask is full).  Host-only;
+ * any output pointer may be NULL. */
+cos_status cos_plan_counts_mask_only(int32_t n, int32_t flags, int64_t *states, int64_t *extensions,
+                                     int64_t *closes);
 
 /* Monte Carlo support (the series coefficients are integrals of the
  * connected sum over vertex sites and times; Methods, diagrammatic

@@ -133,3 +133,44 @@ def brute_unlabelled(A_up, A_dn, w: float = -1.0) -> float:
             if len({find(k) for k in range(n)}) == 1:
                 total += term
     return total
+
+
+def plan_counts(n: int, labelled: bool = False) -> dict:
+    """Reachable states of the DP of :func:`alg1`, by breadth-first search from
+    its start states: number of states, extension transitions, and states
+    that close a cycle (a once-visited interaction exists, or the mask is
+    full)."""
+    labels = (0, 1) if labelled else (0,)
+
+    def visit(mu, k, s):
+        m = list(mu)
+        m[k] = (1 + s) if m[k] == 0 else _TWICE
+        return tuple(m)
+
+    level = {((0, s), (0, s), visit((0,) * n, 0, s)) for s in labels}
+    states = ext = closes = 0
+    for step in range(2 * n):
+        nxt = set()
+        for (u, su), (v, sv), mu in level:
+            states += 1
+            once = [k for k in range(n) if mu[k] not in (0, _TWICE)]
+            if once or step == 2 * n - 1:
+                closes += 1
+            if step == 2 * n - 1:
+                continue
+            blk = v // n
+            for x in range(blk * n, blk * n + n):
+                k = x % n
+                if x == u or mu[k] == _TWICE:
+                    continue
+                for sx in (labels if mu[k] == 0 else (mu[k] - 1,)):
+                    nxt.add(((u, su), (x, sx), visit(mu, k, sx)))
+                    ext += 1
+            if once:
+                k = once[0]
+                sk = mu[k] - 1
+                for h in (k, k + n):
+                    if h != u:
+                        nxt.add(((h, sk), (h, sk), visit(mu, k, sk)))
+        level = nxt
+    return {"states": states, "ext": ext, "closes": closes}

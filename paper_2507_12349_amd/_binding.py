@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcos.so")
 
 UNIFORM, FLAVOUR = 0, 1
-F_STUBS, F_SUBLATTICE = 1, 2
+F_STUBS, F_SUBLATTICE, F_MASK_ONLY = 1, 2, 4
 NMAX, FMAX, NMAX_SUBLATTICE = 12, 16, 8
 
 EXPORTED = (
@@ -25,7 +25,7 @@ EXPORTED = (
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
-    "cos_cdet_workspace", "cos_cdet_su2",
+    "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -51,6 +51,7 @@ def _load():
         "cos_chain_mu_shift": ([i32, p, i32, p, p, p, p, i32, d, p, p, p], i32),
         "cos_plan_counts": ([i32, P64, P64, P64, P64, P64, P64], i32),
         "cos_plan_counts_sublattice": ([i32, P64, P64, P64, P64, P64], i32),
+        "cos_plan_counts_mask_only": ([i32, i32, P64, P64, P64], i32),
         "cos_build_g0_honeycomb": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p], i32),
         "cos_mc_sample": ([i32, i32, i32, d, ctypes.c_uint64, i64, p, p, p], i32),
         "cos_accumulate_moments": ([i32, p, p, p], i32),
@@ -118,6 +119,13 @@ def plan_counts_sublattice(n: int) -> dict:
     return dict(zip(("states", "ext", "closes", "masks", "rows"), [v.value for v in vals]))
 
 
+def plan_counts_mask_only(n: int, sublattice: bool = False) -> dict:
+    vals = [ctypes.c_int64() for _ in range(3)]
+    _check(lib.cos_plan_counts_mask_only(int(n), F_SUBLATTICE if sublattice else 0,
+                                         *[ctypes.byref(v) for v in vals]), "cos_plan_counts_mask_only")
+    return dict(zip(("states", "ext", "closes"), [v.value for v in vals]))
+
+
 def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=None, w: float = -1.0) -> float:
     """One configuration from host arrays (the GPU kernel does the work)."""
     G = np.ascontiguousarray(G, dtype=np.float64)
@@ -133,7 +141,8 @@ def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=N
 class Batch:
     """Plan for a batch of configurations with orders ``n`` (host sequence)."""
 
-    def __init__(self, n, nflav: int, variant: int = UNIFORM, stubs: bool = False, sublattice: bool = False):
+    def __init__(self, n, nflav: int, variant: int = UNIFORM, stubs: bool = False, sublattice: bool = False,
+                 mask_only: bool = False):
         n = np.ascontiguousarray(np.asarray(n, dtype=np.int32).reshape(-1))
         self.n = n
         self.nconf = int(n.size)
@@ -141,10 +150,12 @@ class Batch:
         self.variant = int(variant)
         self.stubs = bool(stubs)
         self.sublattice = bool(sublattice)
+        self.mask_only = bool(mask_only)
         self.nmat = self.nflav if self.variant == FLAVOUR else 1
         self.nstub = self.nmat
         h = ctypes.c_void_p()
-        flags = (F_STUBS if self.stubs else 0) | (F_SUBLATTICE if self.sublattice else 0)
+        flags = ((F_STUBS if self.stubs else 0) | (F_SUBLATTICE if self.sublattice else 0)
+                 | (F_MASK_ONLY if self.mask_only else 0))
         _check(lib.cos_batch_create(self.nconf, _ptr(n), self.nflav, self.variant, flags, ctypes.byref(h)),
                "cos_batch_create")
         self._h = h

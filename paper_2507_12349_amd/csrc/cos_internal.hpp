@@ -130,6 +130,7 @@ struct LvlArgs {
     int64_t F_gstride, F_frows;
     int32_t F_row0;
     int32_t level, group0, nfs, stubs, mpb;
+    int32_t mask_only;        // SU(2) mask-only rules (two spin blocks as the two planes)
     double W;                 // factor of one closed cycle: w * nflav (uniform) or w
     double *out;              // forward, last level: S per configuration (may be null)
     const double *out_bar;    // reverse: dL/dS per configuration

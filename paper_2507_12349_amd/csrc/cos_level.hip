@@ -22,6 +22,16 @@
 //   close: t_m = W sum_{u,l} acc[u]; the next cycle opens at
 //   h = min{k : m_k = 1} with value t_m in every flavour, or S = t_m at the
 //   full mask.
+//
+// Mask-only rules (SU(2), w = -1; Results, the variant without cycle factors;
+// Alg. 1): the states are (head point, current point, mask) with points, not
+// vertices.  They fill the same rows with the two spin blocks as the two
+// planes: row (m, 0) holds the head on the up point of vertex 0 (plane 0)
+// while m_0 = 1, and on its down point (plane 1) once m_0 = 2; rows (m, h),
+// h >= 1, hold both.  The other plane of a row (m, 0) stays empty and is
+// skipped.  A point is reached with weight 1 (no factor 2), never onto the
+// head point; after the first cycle the next one can open only on the down
+// point of vertex 0 (the head is not repeated), later cycles on either end.
 #include "cos_device.hpp"
 
 namespace libcos {
@@ -97,7 +107,7 @@ __global__ void pack_kernel(const PackArgs A) {
 // stay in registers; with several, the flavour loop is outermost and the
 // per-mask sums wait in LDS until every flavour is done.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, bool MASK>
 __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
                                         double *__restrict__ nxt, uint32_t lane8, int64_t cpl, int64_t npl, int lam,
                                         int u, int r, bool start, double sgx, double &cp, double &dext) {
@@ -119,7 +129,7 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
     }
     if (start) {
 #pragma unroll
-        for (int v = 0; v < N; ++v) f[v] = v == 0 ? 1.0 : 0.0;
+        for (int v = 0; v < N; ++v) f[v] = v == 0 ? 1.0 : 0.0;   // mask-only: plane 0 only (plane 1 skipped)
     }
 #pragma unroll
     for (int w = 0; w < N; ++w) {
@@ -131,7 +141,8 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
         if (w == u) cp += a;
         if (twos & bit) continue;
         const bool first = !(ones & bit);
-        double val = first ? 2.0 * a : a;
+        if (MASK && w == 0 && u == 0) continue;   // the head point itself: not an extension
+        double val = first ? (MASK ? a : 2.0 * a) : a;
         if (!first && (cm & bit)) val = __builtin_fma(-sgx, f[w], val);
         if (w == 0 && u == 0 && !(twos & 1u)) {
             dext = val;   // m_0 = 1: the next cycle opens on this same slot
@@ -153,7 +164,12 @@ __device__ __forceinline__ void fwd_close(const MaskRec<N> &M, double *__restric
 
 // with several flavours (kMultiMasks masks per wavefront at most) the close
 // sums of the wave's masks stay in registers across the flavour loop
-template <int N, bool MULTI>
+// mask-only: the plane of row (m, 0) that holds no head point
+__device__ __forceinline__ bool empty_plane(int u, int lam, uint32_t twos) {
+    return u == 0 && ((lam == 0) == ((twos & 1u) != 0u));
+}
+
+template <int N, bool MULTI, bool MASK>
 __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
     double *Gs_all = lds;                      // [N * N][64]
@@ -197,7 +213,9 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
                 int u = 0, slot = 0;
                 double cp = 0.0, dext = 0.0;
                 while (true) {
-                    fwd_row<N>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, M.rb + slot, start, sgx, cp, dext);
+                    if (!(MASK && empty_plane(u, lam, twos)))
+                        fwd_row<N, MASK>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, M.rb + slot, start, sgx, cp,
+                                         dext);
                     if (!hs) break;
                     u = __builtin_ctz(hs);
                     hs &= hs - 1u;
@@ -207,7 +225,7 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
                     cpk[k] += cp;
                     // m_0 = 1 (so h = 0): this flavour's extension into the slot
                     // the next cycle opens on; the close adds to it at the end
-                    if (!last && (ones & 1u)) fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
+                    if (!MASK && !last && (ones & 1u)) fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
                 } else {
                     const double t = A.W * cp;
                     if (last) {
@@ -233,10 +251,16 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
                 const int h = __builtin_ctz(M.ones);
                 const int crow = close_row_base<N>(M, h) + head_slot(h, M.twos | (1u << h));
                 double *dst = nxt + (int64_t)crow * N * 64 + h * 64;
-                for (int lam = 0; lam < nfs; ++lam) {
-                    // h = 0: the slot holds this wave's own extension value (written above)
-                    const double x = h == 0 ? lane_ld(dst + lam * npl, lane8) : 0.0;
-                    lane_st(dst + lam * npl, lane8, t + x);
+                if (MASK) {
+                    // the first cycle's successor opens on the down point of
+                    // vertex 0 only; later ones on both ends of vertex h
+                    for (int lam = (h == 0 ? 1 : 0); lam < nfs; ++lam) lane_st(dst + lam * npl, lane8, t);
+                } else {
+                    for (int lam = 0; lam < nfs; ++lam) {
+                        // h = 0: the slot holds this wave's own extension value (written above)
+                        const double x = h == 0 ? lane_ld(dst + lam * npl, lane8) : 0.0;
+                        lane_st(dst + lam * npl, lane8, t + x);
+                    }
                 }
             }
         }
@@ -257,7 +281,7 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
 // workgroup and flavour; only the (v, w) pairs a row can touch (v current,
 // w open or the head) are accumulated.
 // ---------------------------------------------------------------------------
-template <int N>
+template <int N, bool MASK>
 __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
                                         const double *__restrict__ F, const double *__restrict__ Bn,
                                         double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
@@ -283,7 +307,8 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
         const bool open = !(twos & bit), first = !(ones & bit);
         const int crow = open ? M.crb[w] + head_slot(u, first ? twos : (twos | bit)) : 0;
         const double bc = lane_ld(Bn + (open ? lam * cpl + (int64_t)crow * N * 64 + w * 64 : 0), lane8);
-        a[w] = open ? (first ? 2.0 * bc : bc) : 0.0;
+        a[w] = open ? (first ? (MASK ? bc : 2.0 * bc) : bc) : 0.0;
+        if (MASK && w == 0 && u == 0) a[w] = 0.0;   // no extension onto the head point
         const bool shift = open && !first && (cm & bit);
         sacc = shift ? __builtin_fma(-sc * f[w], bc, sacc) : sacc;
     }
@@ -317,7 +342,7 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
     }
 }
 
-template <int N>
+template <int N, bool MASK>
 __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
     double *Gs_all = lds;                     // [N * N][64]  G of the flavour
@@ -360,15 +385,17 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             } else if (ones) {
                 const int h = __builtin_ctz(ones);
                 const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
-                for (int k = 0; k < nfs; ++k) tb += lane_ld(Bn + k * cpl + (int64_t)crow * N * 64 + h * 64, lane8);
+                for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
+                    tb += lane_ld(Bn + k * cpl + (int64_t)crow * N * 64 + h * 64, lane8);
             }
             tb *= A.W;
             const double sc = (M.code == 1 ? 2.0 : 1.0);
             uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
             int u = 0, slot = 0;
             while (true) {
-                adj_row<N>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start, tb, sg * sc,
-                           sc, sacc);
+                if (!(MASK && empty_plane(u, lam, twos)))
+                    adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start, tb,
+                                     sg * sc, sc, sacc);
                 if (!hs) break;
                 u = __builtin_ctz(hs);
                 hs &= hs - 1u;
@@ -448,12 +475,15 @@ hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups
         const size_t shm = 2 * (size_t)n * n * 64 * sizeof(double);
         const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups);
         switch (n) {
-#define COS_ADJ_CASE(K)                                                              \
-    case K: {                                                                        \
-        hipError_t e = allow_lds((const void *)level_adj_kernel<K>, shm);            \
-        if (e != hipSuccess) return e;                                               \
-        hipLaunchKernelGGL((level_adj_kernel<K>), grid, dim3(64 * wpa), shm, s, a);  \
-        break;                                                                       \
+#define COS_ADJ_CASE(K)                                                                           \
+    case K: {                                                                                     \
+        const void *fn = a.mask_only ? (const void *)level_adj_kernel<K, true>                    \
+                                     : (const void *)level_adj_kernel<K, false>;                  \
+        hipError_t e = allow_lds(fn, shm);                                                        \
+        if (e != hipSuccess) return e;                                                            \
+        if (a.mask_only) hipLaunchKernelGGL((level_adj_kernel<K, true>), grid, dim3(64 * wpa), shm, s, a);  \
+        else hipLaunchKernelGGL((level_adj_kernel<K, false>), grid, dim3(64 * wpa), shm, s, a);             \
+        break;                                                                                    \
     }
             COS_ADJ_CASE(1) COS_ADJ_CASE(2) COS_ADJ_CASE(3) COS_ADJ_CASE(4)
             COS_ADJ_CASE(5) COS_ADJ_CASE(6) COS_ADJ_CASE(7) COS_ADJ_CASE(8)
@@ -470,11 +500,14 @@ hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups
     switch (n) {
 #define COS_FWD_CASE(K)                                                                                    \
     case K: {                                                                                              \
-        hipError_t e = multi ? allow_lds((const void *)level_fwd_kernel<K, true>, shm)                     \
-                             : allow_lds((const void *)level_fwd_kernel<K, false>, shm);                   \
+        const void *fn = a.mask_only ? (const void *)level_fwd_kernel<K, true, true>                       \
+                         : multi     ? (const void *)level_fwd_kernel<K, true, false>                      \
+                                     : (const void *)level_fwd_kernel<K, false, false>;                    \
+        hipError_t e = allow_lds(fn, shm);                                                                 \
         if (e != hipSuccess) return e;                                                                     \
-        if (multi) hipLaunchKernelGGL((level_fwd_kernel<K, true>), grid, dim3(64 * wpb), shm, s, a);       \
-        else hipLaunchKernelGGL((level_fwd_kernel<K, false>), grid, dim3(64 * wpb), shm, s, a);            \
+        if (a.mask_only) hipLaunchKernelGGL((level_fwd_kernel<K, true, true>), grid, dim3(64 * wpb), shm, s, a); \
+        else if (multi) hipLaunchKernelGGL((level_fwd_kernel<K, true, false>), grid, dim3(64 * wpb), shm, s, a); \
+        else hipLaunchKernelGGL((level_fwd_kernel<K, false, false>), grid, dim3(64 * wpb), shm, s, a);           \
         break;                                                                                             \
     }
         COS_FWD_CASE(1) COS_FWD_CASE(2) COS_FWD_CASE(3) COS_FWD_CASE(4)

@@ -17,6 +17,11 @@
 //   close: t_m = W sum_rows acc[(u, s_u)]; the next cycle opens at the lowest
 //   once-visited vertex h with its label s_h (slot (h, s_h) of row (m', h, s_h)),
 //   or S = t_m at the full mask.
+// Mask-only rules (SU(2), Alg. 1 with its labels): the two planes are the spin
+// blocks, as in the unlabelled level kernels: a first visit has weight 1, the
+// head point is never reached by an extension, rows (m, 0, s) use plane 0
+// while m_0 is once-visited and plane 1 afterwards (the other plane is
+// skipped), and the first cycle's successor opens on plane 1 only.
 #include "cos_device.hpp"
 
 namespace libcos {
@@ -53,7 +58,7 @@ __device__ __forceinline__ int sub_child_base(const SubRec<N> &M, int i) {
     return rb;
 }
 
-template <int N>
+template <int N, bool MASK>
 __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
                                             double *__restrict__ nxt, uint32_t lane8, int64_t cpl, int64_t npl,
                                             int lam, int u, int su, int r, bool start, double &cp, double &dext) {
@@ -88,12 +93,14 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
             if (!ext) continue;
             if (!(ones & bit)) {
                 const int crow = M.crb[j] + sub_head_slot(u, su, twos);
-                lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + j * 64, lane8, 2.0 * a);
+                lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + j * 64, lane8, MASK ? a : 2.0 * a);
                 continue;
             }
             const double val = a;
             if (w == 0 && u == 0) {
-                dext = val;   // vertex 0 once visited: the next cycle opens on this same slot
+                // vertex 0 once visited: the next cycle opens on this same slot
+                // (mask-only: the head point itself, not an extension)
+                if (!MASK) dext = val;
                 continue;
             }
             const int crow = (s ? M.crb[2 * w + 1] : M.crb[2 * w]) + sub_head_slot(u, su, twos | bit);
@@ -112,7 +119,7 @@ __device__ __forceinline__ void sub_fwd_close(const SubRec<N> &M, double *__rest
     lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * h + sh) * 64, lane8, t + (h == 0 ? dext : 0.0));
 }
 
-template <int N, bool MULTI>
+template <int N, bool MULTI, bool MASK>
 __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
     constexpr int D = 2 * N;
     extern __shared__ double lds[];
@@ -153,7 +160,10 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
                 int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
                 double cp = 0.0, dext = 0.0;
                 while (true) {
-                    sub_fwd_row<N>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, su, M.rb + slot, start, cp, dext);
+                    // mask-only: rows of head vertex 0 use one plane (plane 0 while m_0 is once-visited)
+                    if (!(MASK && u == 0 && ((lam == 0) == full0)))
+                        sub_fwd_row<N, MASK>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, su, M.rb + slot, start, cp,
+                                             dext);
                     ++slot;
                     if (full0 && su == 0) {
                         su = 1;
@@ -166,7 +176,7 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
                 }
                 if (MULTI) {
                     cpk[k] += cp;
-                    if (!last && (ones & 1u)) sub_fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
+                    if (!MASK && !last && (ones & 1u)) sub_fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
                 } else {
                     const double t = A.W * cp;
                     if (last) {
@@ -193,10 +203,14 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
                 const int sh = (M.subb >> h) & 1u;
                 const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, M.twos | (1u << h));
                 double *dst = nxt + (int64_t)crow * D * 64 + (2 * h + sh) * 64;
-                for (int lam = 0; lam < nfs; ++lam) {
-                    // h = 0: the slot holds this wave's own extension value (written above)
-                    const double x = h == 0 ? lane_ld(dst + lam * npl, lane8) : 0.0;
-                    lane_st(dst + lam * npl, lane8, t + x);
+                if (MASK) {
+                    for (int lam = (h == 0 ? 1 : 0); lam < nfs; ++lam) lane_st(dst + lam * npl, lane8, t);
+                } else {
+                    for (int lam = 0; lam < nfs; ++lam) {
+                        // h = 0: the slot holds this wave's own extension value (written above)
+                        const double x = h == 0 ? lane_ld(dst + lam * npl, lane8) : 0.0;
+                        lane_st(dst + lam * npl, lane8, t + x);
+                    }
                 }
             }
         }
@@ -218,11 +232,14 @@ hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb,
     switch (n) {
 #define COS_SUB_CASE(K)                                                                                  \
     case K: {                                                                                            \
-        hipError_t e = multi ? allow_sub_lds((const void *)sub_fwd_kernel<K, true>, shm)                 \
-                             : allow_sub_lds((const void *)sub_fwd_kernel<K, false>, shm);               \
+        const void *fn = a.mask_only ? (const void *)sub_fwd_kernel<K, true, true>                       \
+                         : multi     ? (const void *)sub_fwd_kernel<K, true, false>                      \
+                                     : (const void *)sub_fwd_kernel<K, false, false>;                    \
+        hipError_t e = allow_sub_lds(fn, shm);                                                           \
         if (e != hipSuccess) return e;                                                                   \
-        if (multi) hipLaunchKernelGGL((sub_fwd_kernel<K, true>), grid, dim3(64 * wpb), shm, s, a);       \
-        else hipLaunchKernelGGL((sub_fwd_kernel<K, false>), grid, dim3(64 * wpb), shm, s, a);            \
+        if (a.mask_only) hipLaunchKernelGGL((sub_fwd_kernel<K, true, true>), grid, dim3(64 * wpb), shm, s, a); \
+        else if (multi) hipLaunchKernelGGL((sub_fwd_kernel<K, true, false>), grid, dim3(64 * wpb), shm, s, a); \
+        else hipLaunchKernelGGL((sub_fwd_kernel<K, false, false>), grid, dim3(64 * wpb), shm, s, a);           \
         break;                                                                                           \
     }
         COS_SUB_CASE(1) COS_SUB_CASE(2) COS_SUB_CASE(3) COS_SUB_CASE(4)

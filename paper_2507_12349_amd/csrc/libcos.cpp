@@ -299,11 +299,24 @@ cos_status check_device(int *dev, int *ncu) {
 cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
     if (variant != COS_UNIFORM && variant != COS_FLAVOUR)
         return fail(COS_EINVAL, "variant must be COS_UNIFORM (0) or COS_FLAVOUR (1), got %d", variant);
-    if (flags & ~(COS_F_STUBS | COS_F_SUBLATTICE))
-        return fail(COS_EINVAL, "unknown flag bits 0x%x", flags & ~(COS_F_STUBS | COS_F_SUBLATTICE));
+    const int32_t known = COS_F_STUBS | COS_F_SUBLATTICE | COS_F_MASK_ONLY;
+    if (flags & ~known) return fail(COS_EINVAL, "unknown flag bits 0x%x", flags & ~known);
     if ((flags & COS_F_STUBS) && (flags & COS_F_SUBLATTICE))
         return fail(COS_EINVAL, "COS_F_STUBS cannot be combined with COS_F_SUBLATTICE");
     if (nflav < 1 || nflav > COS_FMAX) return fail(COS_ERANGE, "nflav must be in [1, %d], got %d", COS_FMAX, nflav);
+    if (flags & COS_F_MASK_ONLY) {
+        if (variant != COS_FLAVOUR || nflav != 2)
+            return fail(COS_EINVAL, "COS_F_MASK_ONLY needs COS_FLAVOUR with nflav = 2 (the two spin blocks)");
+        if (flags & COS_F_STUBS) return fail(COS_EINVAL, "COS_F_MASK_ONLY cannot be combined with COS_F_STUBS");
+    }
+    return COS_OK;
+}
+
+// the mask-only variant keeps non-physical clows, which cancel only through
+// the fermion sign of a cycle
+cos_status check_weight(int32_t flags, double cycle_weight) {
+    if ((flags & COS_F_MASK_ONLY) && cycle_weight != -1.0)
+        return fail(COS_EINVAL, "COS_F_MASK_ONLY needs cycle_weight = -1, got %g", cycle_weight);
     return COS_OK;
 }
 
@@ -416,6 +429,61 @@ cos_status cos_plan_counts_sublattice(int32_t n, int64_t *states, int64_t *exten
     if (closes) *closes = p->closes;
     if (masks) *masks = (int64_t)p->masks.size();
     if (rows) *rows = (int64_t)p->rows.size();
+    return COS_OK;
+}
+
+cos_status cos_plan_counts_mask_only(int32_t n, int32_t flags, int64_t *states, int64_t *extensions,
+                                     int64_t *closes) {
+    if (flags & ~COS_F_SUBLATTICE) return fail(COS_EINVAL, "flags may only hold COS_F_SUBLATTICE, got 0x%x", flags);
+    const bool sub = (flags & COS_F_SUBLATTICE) != 0;
+    const int nmax = sub ? COS_NMAX_SUBLATTICE : COS_NMAX;
+    if (n < 1 || n > nmax) return fail(COS_ERANGE, "n must be in [1, %d], got %d", nmax, n);
+    // the slots the level kernels visit in mask-only mode: rows (m, u[, s_u])
+    // with the plane of head vertex 0 fixed by m_0, current slots from the
+    // closed-form tables
+    const int base = sub ? 4 : 3;
+    int64_t ncodes = 1;
+    for (int k = 0; k < n; ++k) ncodes *= base;
+    int64_t st = 0, ex = 0, cl = 0;
+    for (int64_t code = 0; code < ncodes; ++code) {
+        uint32_t ones = 0, twos = 0, subb = 0;
+        int64_t c = code;
+        for (int k = 0; k < n; ++k) {
+            const int d = (int)(c % base);
+            c /= base;
+            if (d == base - 1) {
+                twos |= 1u << k;   // visited twice
+            } else if (d != 0) {
+                ones |= 1u << k;   // visited once (labelled: digit 1 on A, 2 on B)
+                if (d == 2) subb |= 1u << k;
+            }
+        }
+        if (!((ones | twos) & 1u)) continue;   // vertex 0 is visited first
+        const bool full = twos == (1u << n) - 1u;
+        int open_pts = 0;   // extension targets of one slot (points, with their labels)
+        for (int w = 0; w < n; ++w)
+            if (!((twos >> w) & 1u)) open_pts += (sub && !((ones >> w) & 1u)) ? 2 : 1;
+        for (int u = 0; u < n; ++u) {
+            if (u > 0 && !((twos & 1u) && ((twos >> u) & 1u))) continue;
+            const int nlab = sub ? ((u == 0 && (ones & 1u)) ? 1 : 2) : 1;
+            for (int li = 0; li < nlab; ++li) {
+                const int su = (sub && u == 0 && (ones & 1u)) ? (int)(subb & 1u) : li;
+                for (int b = 0; b < 2; ++b) {
+                    if (u == 0 && ((b == 0) == ((twos & 1u) != 0u))) continue;   // empty plane
+                    const uint32_t cs = sub ? sub_current(n, u, su, ones, twos, subb) : current_set(u, ones, twos);
+                    const int nc = __builtin_popcount(cs);
+                    // no extension onto the head point of the first cycle
+                    const int e = open_pts - ((u == 0 && (ones & 1u)) ? 1 : 0);
+                    st += nc;
+                    ex += (int64_t)nc * e;
+                    if (ones || full) cl += nc;
+                }
+            }
+        }
+    }
+    if (states) *states = st;
+    if (extensions) *extensions = ex;
+    if (closes) *closes = cl;
     return COS_OK;
 }
 
@@ -553,6 +621,7 @@ static LvlArgs level_args(cos_batch_t b, const OrderGroup &o, double cycle_weigh
     a.nfs = b->nfs;
     a.stubs = (b->flags & COS_F_STUBS) ? 1 : 0;
     a.W = cycle_weight * (b->variant == COS_UNIFORM ? (double)b->nflav : 1.0);
+    a.mask_only = (b->flags & COS_F_MASK_ONLY) ? 1 : 0;
     return a;
 }
 
@@ -609,6 +678,7 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
                                      void *stream) {
     cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
     if (st) return st;
+    if ((st = check_weight(b->flags, cycle_weight))) return st;
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
     hipStream_t s = (hipStream_t)stream;
     for (const OrderGroup &o : b->orders)
@@ -711,6 +781,7 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
                                      double *d_stub_bar, void *stream) {
     cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
     if (st) return st;
+    if ((st = check_weight(b->flags, cycle_weight))) return st;
     if (!d_out_bar || !d_G_bar) return fail(COS_EINVAL, "d_out_bar and d_G_bar are required");
     if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
     if (b->flags & COS_F_SUBLATTICE) return fail(COS_EUNSUPPORTED, "the reverse sweep of sublattice batches is not built");
@@ -754,6 +825,7 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
                               double *d_stub_bar, void *stream) {
     cos_status st = check_batch_ptrs(b, d_G, d_Goff, d_stub);
     if (st) return st;
+    if ((st = check_weight(b->flags, cycle_weight))) return st;
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
     if (d_out_bar) {
         if (!d_G_bar) return fail(COS_EINVAL, "d_G_bar is required to tune the reverse sweep");

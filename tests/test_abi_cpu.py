@@ -55,6 +55,16 @@ def test_sublattice_plan_counts_match_oracle(B, n):
         (o["states"], o["ext"], o["closes"], o["masks"], o["rows"])
 
 
+@pytest.mark.parametrize("n,labelled", [(k, False) for k in range(1, 8)] + [(k, True) for k in range(1, 6)])
+def test_mask_only_plan_counts_match_oracle(B, n, labelled):
+    """The slots the level kernels visit in mask-only mode (rows with the
+    plane of head vertex 0 fixed by its mask digit, closed-form current slots)
+    are exactly the states of Alg. 1's DP reachable from its start, found by
+    the oracle's breadth-first search."""
+    from oracle import maskonly
+    assert B.plan_counts_mask_only(n, labelled) == maskonly.plan_counts(n, labelled)
+
+
 def _st(B, code):
     return B.lib.cos_status_string(code).decode()
 
@@ -77,6 +87,14 @@ def test_argument_validation_without_device(B):
     big = np.array([4, 9], dtype=np.int32)
     assert lib.cos_batch_create(2, big.ctypes.data, 2, 0, 2, ctypes.byref(h)) == -2  # above the sublattice max
     assert lib.cos_plan_counts_sublattice(9, None, None, None, None, None) == -2
+    # mask-only: two spin blocks (COS_FLAVOUR, nflav = 2), no shifts
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 4, ctypes.byref(h)) == -1   # uniform variant
+    assert lib.cos_batch_create(2, n.ctypes.data, 3, 1, 4, ctypes.byref(h)) == -1   # three flavours
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 1, 5, ctypes.byref(h)) == -1   # with shifts
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 1, 8, ctypes.byref(h)) == -1   # unknown flag
+    assert lib.cos_plan_counts_mask_only(13, 0, None, None, None) == -2
+    assert lib.cos_plan_counts_mask_only(9, 2, None, None, None) == -2
+    assert lib.cos_plan_counts_mask_only(4, 1, None, None, None) == -1
     bad = np.array([4, 13], dtype=np.int32)
     assert lib.cos_batch_create(2, bad.ctypes.data, 2, 0, 0, ctypes.byref(h)) == -2
     assert "n[1] = 13" in lib.cos_last_error().decode()
