@@ -101,6 +101,23 @@ def honeycomb_forward(B, torch, reps):
     states_bytes = w.nflav * 16.0 * pc["states"]                # each state written once, read once
     shape = b.launch_shape(nn)
     b.close()
+    # the same sum by the mask-only variant (Alg. 1 with its labels)
+    bm = B.Batch(d.n, w.nflav, 1, sublattice=True, mask_only=True)
+    Sm = torch.empty_like(S)
+    bm.autotune(G, Goff, None, -1.0, Sm, stream=stream)
+    torch.cuda.synchronize()
+    m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    m0.record(stream)
+    for _ in range(reps):
+        bm.forward(G, Goff, None, -1.0, Sm, stream)
+    m1.record(stream)
+    torch.cuda.synchronize()
+    bm.close()
+    ref = S / float(2 ** nn)
+    mask_only = {"forward_levels_ms": m0.elapsed_time(m1) / reps,
+                 "configs_per_s_forward_levels": n.size / (m0.elapsed_time(m1) / reps * 1e-3),
+                 "max_rel_diff_from_labelled_sum": float(((Sm - ref).abs() / ref.abs().clamp_min(1e-300)).max()),
+                 "states_per_config": B.plan_counts_mask_only(nn, True)["states"]}
     cdet = cdet_comparison(B, torch, G, S, n.size, nn, w.nflav, stream)
     return {"workload": "honeycomb: 16x16 cells, beta=5, SU(2) flavour-dependent (staggered field +-0.3), "
                         "mu=0.3, n=8, %d configs, sublattice labels summed (2n x 2n matrices)" % n.size,
@@ -110,7 +127,60 @@ def honeycomb_forward(B, torch, reps):
             "frac_of_fp64_peak": flop * n.size / (fwd_ms * 1e-3) / PEAK_FP64,
             "state_stream_bytes_per_config": states_bytes,
             "state_stream_TBps": states_bytes * n.size / (fwd_ms * 1e-3) / 1e12,
+            "mask_only_alg1": mask_only,
             "cdet_comparison": cdet}
+
+
+def mask_only_su2(B, torch, reps):
+    """The mask-only variant (Alg. 1) against the vertex-level two-flavour path
+    on the same SU(2) propagators: the adjoint workload's configurations
+    (8x8, beta=4, n=10, 2048) with mu=-0.5 for both spins; forward + reverse
+    sweep each, autotuned; the two sums agree up to the factor 2^n."""
+    from paper_2507_12349_amd.autograd import Geometry
+    from paper_2507_12349_amd.workloads import draw
+    d = draw(WORKLOAD)
+    w = d.workload
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    nconf, n = int(d.n.size), int(d.n[0])
+    geo = Geometry(d, 2, dev)
+    G = torch.empty(geo.total, dtype=torch.float64, device=dev)
+    dG = torch.empty_like(G)
+    B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, np.array([w.mu[0]] * 2),
+               np.zeros(2), geo.Goff, G, dG, stream)
+    ob = torch.ones(nconf, dtype=torch.float64, device=dev)
+    res = {}
+    outs = {}
+    for name, mask in (("mask_only", True), ("vertex_two_flavour", False)):
+        b = B.Batch(d.n, 2, B.FLAVOUR, mask_only=mask)
+        S = torch.empty(nconf, dtype=torch.float64, device=dev)
+        Gb = torch.empty_like(G)
+        b.autotune(G, geo.Goff, None, -1.0, S, ob, Gb, None, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(reps):
+            b.forward(G, geo.Goff, None, -1.0, S, stream)
+        f1.record(stream)
+        e0.record(stream)
+        for _ in range(reps):
+            b.adjoint(G, geo.Goff, None, -1.0, ob, S, Gb, None, stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        outs[name] = S.clone() / (1.0 if mask else float(2 ** n))
+        res[name] = {"forward_configs_per_s": nconf / (f0.elapsed_time(f1) / reps * 1e-3),
+                     "fwd_adjoint_configs_per_s": nconf / (e0.elapsed_time(e1) / reps * 1e-3),
+                     "launch_shape": b.launch_shape(n)}
+        b.close()
+    pm, pv = B.plan_counts_mask_only(n), B.plan_counts(n)
+    res["states_per_config"] = {"mask_only": pm["states"], "vertex_two_flavour": 2 * pv["states"]}
+    res["extensions_per_config"] = {"mask_only": pm["ext"], "vertex_two_flavour": 2 * pv["ext"]}
+    a, v = outs["mask_only"], outs["vertex_two_flavour"]
+    res["max_rel_diff_of_sums"] = float(((a - v).abs() / v.abs().clamp_min(1e-300)).max())
+    res["workload"] = ("adjoint workload's configurations as SU(2): 8x8, beta=4, mu=-0.5 both spins, n=%d, "
+                       "%d configs; the vertex-level sum divided by 2^n" % (n, nconf))
+    return res
 
 
 def cdet_comparison(B, torch, G, S, nconf, n, nflav, stream):
@@ -205,6 +275,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="default launch shapes instead of autotuned ones")
     ap.add_argument("--no-honeycomb", action="store_true", help="skip the sublattice (honeycomb) measurement")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo series measurement")
+    ap.add_argument("--no-mask-only", action="store_true", help="skip the SU(2) mask-only comparison")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
@@ -381,6 +452,7 @@ def main():
 
     hc = None if args.no_honeycomb else honeycomb_forward(B, torch, max(3, args.steps // 2))
     mcs = None if args.no_mc else mc_series(torch)
+    mo = None if args.no_mask_only else mask_only_su2(B, torch, max(3, args.steps // 2))
 
     cpu = None
     if not args.no_cpu:
@@ -427,6 +499,7 @@ def main():
                      "forward_kernel_tflops": flop_fwd * nconf / (phases["forward"] / args.steps * 1e-3) / 1e12},
         "sublattice_honeycomb_forward": hc,
         "mc_series": mcs,
+        "su2_mask_only_vs_vertex": mo,
         "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
