@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12           # MI355X FP64 vector peak, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, bytes/s
-REV_KERNEL = "level_adj_kernel<%d>"
+REV_KERNEL = "level_adj_kernel<%d, false>"
 WORKLOAD = "adjoint"
 
 
@@ -122,7 +122,7 @@ def honeycomb_forward(B, torch, reps):
     return {"workload": "honeycomb: 16x16 cells, beta=5, SU(2) flavour-dependent (staggered field +-0.3), "
                         "mu=0.3, n=8, %d configs, sublattice labels summed (2n x 2n matrices)" % n.size,
             "configs_per_s": n.size / (ms * 1e-3), "ms_per_batch_incl_g0": ms, "forward_levels_ms": fwd_ms,
-            "kernel": "sub_fwd_kernel<8,true>", "launch_shape": shape,
+            "kernel": "sub_fwd_kernel<8, true, false>", "launch_shape": shape,
             "flop_per_config": flop, "forward_tflops": flop * n.size / (fwd_ms * 1e-3) / 1e12,
             "frac_of_fp64_peak": flop * n.size / (fwd_ms * 1e-3) / PEAK_FP64,
             "state_stream_bytes_per_config": states_bytes,
