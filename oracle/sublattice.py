@@ -16,6 +16,7 @@ Argument convention: ``A`` has shape (2n, 2n) (variant U) or (nf, 2n, 2n)
   :func:`by_assignment`   the definition: sum over the 2^n label assignments
                           of the connected sum of the n x n matrix they pick
                           (oracle O3 per assignment)
+  :func:`by_assignment_adjoint`  the same with the O3 reverse sweep: dS/dA
   :func:`brute_labeled`   independent enumeration of labelled permutations
                           (pure Python, n <= 3)
   :func:`alg1_brute`      the SU(2) form of Alg. 1 (up and down point per
@@ -47,6 +48,23 @@ def by_assignment(A, nf: int, variant: int = 0, w: float = -1.0, precision: str 
     for s in itertools.product((0, 1), repeat=n):
         tot += oracle.dp(pick(A, s), nf, variant, None, w, precision)
     return tot
+
+
+def by_assignment_adjoint(A, nf: int, variant: int = 0, w: float = -1.0):
+    """(S, dS/dA) of :func:`by_assignment`: for each label assignment the
+    oracle O3 reverse sweep of the matrix it picks, added back into the
+    entries it was picked from."""
+    import oracle
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[-1] // 2
+    tot = 0.0
+    grad = np.zeros_like(A)
+    for s in itertools.product((0, 1), repeat=n):
+        idx = 2 * np.arange(n) + np.asarray(s, dtype=np.int64)
+        S, g, _ = oracle.dp_adjoint(pick(A, s), nf, variant, None, w)
+        tot += S
+        grad[..., idx[:, None], idx[None, :]] += g
+    return tot, grad
 
 
 def brute_labeled(A, nf: int, variant: int = 0, w: float = -1.0) -> float:

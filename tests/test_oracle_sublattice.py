@@ -77,3 +77,21 @@ def test_alg1_is_two_flavour_sum_over_2n(oracle_mod, n):
     got = SL.alg1_brute(A[0], A[1])
     ref = SL.by_assignment(A, 2, 1) / 2 ** n
     assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (got, ref)
+
+
+@pytest.mark.parametrize("n,nf,variant", [(2, 2, 0), (3, 2, 1), (3, 3, 0)])
+def test_assignment_adjoint_against_central_differences(oracle_mod, n, nf, variant):
+    """dS/dA of the labelled sum: S is a polynomial of degree at most 2 in
+    each entry (both points of a vertex can carry the same matrix entry), so a
+    central difference is exact up to rounding."""
+    rng = np.random.default_rng(90 + 10 * n + variant)
+    A = rng.normal(size=(2 * n, 2 * n)) if variant == 0 else rng.normal(size=(nf, 2 * n, 2 * n))
+    S, g = SL.by_assignment_adjoint(A, nf, variant)
+    assert S == pytest.approx(SL.by_assignment(A, nf, variant), rel=1e-13, abs=1e-14)
+    h = 1e-5
+    for idx in np.ndindex(A.shape):
+        P, M = A.copy(), A.copy()
+        P[idx] += h
+        M[idx] -= h
+        fd = (SL.by_assignment(P, nf, variant) - SL.by_assignment(M, nf, variant)) / (2 * h)
+        assert abs(g[idx] - fd) <= 1e-7 * max(1.0, abs(fd)), (idx, g[idx], fd)
