@@ -74,9 +74,9 @@ enum { COS_UNIFORM = 0, COS_FLAVOUR = 1 };
  * pass.  Matrices are then 2n x 2n per configuration and flavour, row-major,
  * index 2k + s (s = 0 for A, 1 for B): entry [2k+s][2j+t] is the propagator
  * from vertex k on sublattice s to vertex j on sublattice t.  Orders up to
- * COS_NMAX_SUBLATTICE; forward sums only (the adjoint and the autotuner's
- * reverse sweep return COS_EUNSUPPORTED); not combinable with COS_F_STUBS
- * (shifts enter through the matrices' diagonals). */
+ * COS_NMAX_SUBLATTICE; forward sums and the reverse sweep (d_G_bar in the
+ * same 2n x 2n layout); not combinable with COS_F_STUBS (shifts enter through
+ * the matrices' diagonals). */
 /* COS_F_MASK_ONLY: the SU(2) mask-only variant (Results, the variant for
  * cycles without extra factors; Methods, Alg. 1).  The DP works on points
  * (each vertex k has an up point and a down point, one per spin block) and
@@ -90,8 +90,8 @@ enum { COS_UNIFORM = 0, COS_FLAVOUR = 1 };
  * cancellation needs the fermion sign; other weights return COS_EINVAL);
  * not combinable with COS_F_STUBS.  The result is the SU(2) connected sum,
  * 2^-n times the COS_FLAVOUR two-flavour sum of the same matrices.  With
- * COS_F_SUBLATTICE it is Alg. 1 with its sublattice labels (forward only).
- * The reverse sweep is available without COS_F_SUBLATTICE. */
+ * COS_F_SUBLATTICE it is Alg. 1 with its sublattice labels.  Forward sums
+ * and the reverse sweep. */
 enum { COS_F_STUBS = 1, COS_F_SUBLATTICE = 2, COS_F_MASK_ONLY = 4 };
 
 typedef struct cos_batch_s *cos_batch_t;

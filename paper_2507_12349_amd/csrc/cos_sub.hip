@@ -217,6 +217,158 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// reverse: B = dS/dF of the labelled states at `level` from B at level + 1,
+// the transpose of the forward rules above:
+//   a[(w, s)] = c B(child)[(w, s)] for every output the row extends to
+//   (c = 2 on a first visit, 1 otherwise and in mask-only mode), plus
+//   W tbar_m on the row's close slot (u, s_u);
+//   tbar_m = sum_l B(m', h, s_h, l)[(h, s_h)] of the slot the next cycle opens
+//   on (1 at the full mask), B(m, u, s_u)[i] = sum_j G[i][j] a[j] over the
+//   current slots i, and dS/dG[i][j] += f[i] a[j].
+// A wavefront owns whole rows; the dS/dG accumulator of the workgroup's 64
+// configurations sits in LDS ([i][j][lane], 128 KB at n = 8) and is added to
+// the packed gradient once per workgroup and flavour.  G itself is read from
+// LDS when both fit (n <= 6) and from global memory (L2-resident: one
+// group's matrices) above that.
+// ---------------------------------------------------------------------------
+template <int N, bool MASK, bool GLDS>
+__device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, const double *__restrict__ Gg, uint32_t gaddr,
+                                            uint32_t gbaddr, const double *__restrict__ F,
+                                            const double *__restrict__ Bn, double *__restrict__ Bc, uint32_t lane8,
+                                            int64_t fpl, int64_t cpl, int64_t npl, int lam, int u, int su, int r,
+                                            bool start, double tb) {
+    constexpr int D = 2 * N;
+    const uint32_t ones = M.ones, twos = M.twos, subb = M.subb;
+    const uint32_t cs = sub_current(N, u, su, ones, twos, subb);
+    const int i0 = cs ? __builtin_ctz(cs) : 0;   // every reachable row has a current slot; guard anyway
+    const double *__restrict__ src = F + lam * fpl + (int64_t)r * D * 64;
+    // straight-line loads with selects (unused ones re-read a needed slot)
+    double f[D], a[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const bool c = (cs >> i) & 1u;
+        const double x = lane_ld(src + (c ? i : i0) * 64, lane8);
+        f[i] = start ? (i == su ? 1.0 : 0.0) : (c ? x : 0.0);   // start: vertex 0 on label s_u
+    }
+    uint32_t need = 0;   // outputs j with a[j] possibly nonzero (wave-uniform)
+#pragma unroll
+    for (int w = 0; w < N; ++w) {
+        const uint32_t bit = 1u << w;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int j = 2 * w + s;
+            const bool once = ones & bit;
+            bool ext = !(twos & bit) && (!once || (int)((subb >> w) & 1u) == s);
+            if (MASK && once && w == 0 && u == 0) ext = false;   // the head point itself
+            const int crow = ext ? M.crb[j] + sub_head_slot(u, su, once ? (twos | bit) : twos) : 0;
+            const double bc = lane_ld(Bn + (ext ? lam * cpl + (int64_t)crow * D * 64 + j * 64 : 0), lane8);
+            a[j] = ext ? ((!once && !MASK) ? 2.0 * bc : bc) : 0.0;
+            if (ext) need |= 1u << j;
+        }
+    }
+    const int jc = 2 * u + su;   // the row's close slot
+    a[jc] += tb;
+    need |= 1u << jc;
+    asm volatile("" : "+v"(gaddr));
+    asm volatile("" : "+v"(gbaddr));
+    const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
+    lds_double *Gb = (lds_double *)(uintptr_t)gbaddr;
+    double *__restrict__ dst = Bc + lam * npl + (int64_t)r * D * 64;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        if (!((cs >> i) & 1u)) continue;   // wave-uniform
+        double b = 0.0;
+#pragma unroll
+        for (int j = 0; j < D; ++j) {
+            if (!((need >> j) & 1u)) continue;   // wave-uniform
+            const double g = GLDS ? (double)Gs[(i * D + j) * 64] : lane_ld(Gg + (i * D + j) * 64, lane8);
+            b = __builtin_fma(g, a[j], b);
+        }
+        lane_st(dst + i * 64, lane8, b);
+#pragma unroll
+        for (int j = 0; j < D; ++j)
+            if ((need >> j) & 1u)   // wave-uniform
+                __hip_atomic_fetch_add(Gb + (i * D + j) * 64, f[i] * a[j], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+template <int N, bool MASK>
+__global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
+    constexpr int D = 2 * N;
+    constexpr bool GLDS = 2 * D * D * 64 * 8 <= 160 * 1024;   // G and the accumulator both in LDS
+    extern __shared__ double lds[];
+    double *Gb_all = lds;                      // [D * D][64]  dS/dG of the flavour, this workgroup
+    double *Gs_all = lds + D * D * 64;         // [D * D][64]  G of the flavour (GLDS only)
+    const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
+    const int wpb = blockDim.x >> 6;
+    const DevPlan &P = A.plan;
+    const int4 L = load_level(P, A.level);
+    const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
+    const int mb1 = min(mb0 + A.mpb, L.w);    // may be empty: the wave still joins the barriers
+    const int gl = blockIdx.y, g = A.group0 + gl;
+    const int nfs = A.nfs;
+    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * D * 64;
+    const int64_t fpl = A.F_frows * D * 64, cpl = A.cur_frows * D * 64, npl = A.nxt_frows * D * 64;
+    const double *__restrict__ Bn = A.cur + gl * A.cur_gstride;   // level + 1
+    double *__restrict__ Bc = A.nxt + gl * A.nxt_gstride;         // level
+    const uint32_t lane8 = (uint32_t)lane * 8u;
+    const int cfg = A.lane_cfg[g * 64 + lane];
+    const double obar = cfg >= 0 ? A.out_bar[cfg] : 0.0;
+    const uint32_t gaddr = lds_addr(Gs_all) + lane * 8u, gbaddr = lds_addr(Gb_all) + lane * 8u;
+    const bool top = A.level == 2 * N, start = A.level == 1;
+
+    for (int lam = 0; lam < nfs; ++lam) {
+        __syncthreads();   // the previous flavour's accumulator has been flushed
+        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * D * D * 64;
+        for (int i = threadIdx.x; i < D * D * 64; i += blockDim.x) {
+            if (GLDS) Gs_all[i] = gsrc[i];
+            Gb_all[i] = 0.0;
+        }
+        __syncthreads();
+        for (int mi = mb0; mi < mb1; ++mi) {
+            const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
+            const uint32_t ones = M.ones, twos = M.twos;
+            double tb = 0.0;
+            if (top) {
+                tb = obar;
+            } else if (ones) {
+                const int h = __builtin_ctz(ones);
+                const int sh = (M.subb >> h) & 1u;
+                const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, twos | (1u << h));
+                // mask-only: the first cycle's successor lives on plane 1 only
+                for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
+                    tb += lane_ld(Bn + k * cpl + (int64_t)crow * D * 64 + (2 * h + sh) * 64, lane8);
+            }
+            tb *= A.W;
+            const bool full0 = twos & 1u;
+            uint32_t hs = full0 ? (twos & ~1u) : 0u;   // heads >= 1, ascending
+            int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
+            while (true) {
+                if (!(MASK && u == 0 && ((lam == 0) == full0)))
+                    sub_adj_row<N, MASK, GLDS>(M, gsrc, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, su,
+                                               M.rb + slot, start, tb);
+                ++slot;
+                if (full0 && su == 0) {
+                    su = 1;
+                    continue;
+                }
+                if (!hs) break;
+                u = __builtin_ctz(hs);
+                hs &= hs - 1u;
+                su = 0;
+            }
+        }
+        __syncthreads();
+        double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64;
+        for (int i = threadIdx.x; i < D * D * 64; i += blockDim.x) {
+            const double x = Gb_all[i];
+            if (x != 0.0) atomicAdd(gb + i, x);
+        }
+    }
+}
+
 static hipError_t allow_sub_lds(const void *fn, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
@@ -245,6 +397,31 @@ hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb,
         COS_SUB_CASE(1) COS_SUB_CASE(2) COS_SUB_CASE(3) COS_SUB_CASE(4)
         COS_SUB_CASE(5) COS_SUB_CASE(6) COS_SUB_CASE(7) COS_SUB_CASE(8)
 #undef COS_SUB_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipStream_t s) {
+    const int n = a.plan.n;
+    const int wpa = adj_waves_per_block();
+    const size_t side = 2 * (size_t)n, mat = side * side * 64 * sizeof(double);
+    const size_t shm = (2 * mat <= 160 * 1024) ? 2 * mat : mat;   // G in LDS too when both fit
+    const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups);
+    switch (n) {
+#define COS_SUBADJ_CASE(K)                                                                               \
+    case K: {                                                                                            \
+        const void *fn = a.mask_only ? (const void *)sub_adj_kernel<K, true>                             \
+                                     : (const void *)sub_adj_kernel<K, false>;                           \
+        hipError_t e = allow_sub_lds(fn, shm);                                                           \
+        if (e != hipSuccess) return e;                                                                   \
+        if (a.mask_only) hipLaunchKernelGGL((sub_adj_kernel<K, true>), grid, dim3(64 * wpa), shm, s, a); \
+        else hipLaunchKernelGGL((sub_adj_kernel<K, false>), grid, dim3(64 * wpa), shm, s, a);            \
+        break;                                                                                           \
+    }
+        COS_SUBADJ_CASE(1) COS_SUBADJ_CASE(2) COS_SUBADJ_CASE(3) COS_SUBADJ_CASE(4)
+        COS_SUBADJ_CASE(5) COS_SUBADJ_CASE(6) COS_SUBADJ_CASE(7) COS_SUBADJ_CASE(8)
+#undef COS_SUBADJ_CASE
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -691,14 +691,14 @@ static cos_status prepare_adjoint(cos_batch_t b) {
     if (b->d_Fall) return COS_OK;
     int64_t fall = 0, gb = 0, sb = 0;
     for (OrderGroup &o : b->orders) {
-        const int64_t rs = (int64_t)b->nfs * o.n * 64;
+        const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
         // all forward levels and two adjoint windows
         const int64_t per_group = ((int64_t)o.hp->rows.size() + 2 * (int64_t)o.hp->max_rows) * rs;
         o.chunk_adj = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
         fall = std::max(fall, per_group * o.chunk_adj);
         o.gb_off = gb;
         o.sb_off = sb;
-        gb += (int64_t)o.ngroups * b->nfs * o.n * o.n * 64;
+        gb += (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
         sb += (int64_t)o.ngroups * b->nfs * 64;
     }
     if (hipMalloc((void **)&b->d_Fall, sizeof(double) * fall) != hipSuccess) {
@@ -724,10 +724,11 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
     HIP_TRY(tmark(b, COS_PHASE_PACK, s));
     HIP_TRY(launch_pack(pa, s));
     double *GbT = b->d_GbT + o.gb_off, *sbT = b->d_sbT + o.sb_off;
-    const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.n * o.n * 64, nsb = (int64_t)o.ngroups * b->nfs * 64;
+    const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
+    const int64_t nsb = (int64_t)o.ngroups * b->nfs * 64;
     HIP_TRY(launch_zero(GbT, ngb, s));
     HIP_TRY(launch_zero(sbT, nsb, s));
-    const int64_t rs = (int64_t)b->nfs * o.n * 64;
+    const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
     const int64_t total_rows = (int64_t)o.hp->rows.size();
     const int64_t fstride = total_rows * rs, bstride = (int64_t)o.hp->max_rows * rs;
     for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_adj) {
@@ -747,7 +748,8 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
             const int nm = o.hp->levels[l].w;
             a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
             a.out = d_out;
-            HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            if (o.sub) HIP_TRY(launch_sub_level(a, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            else HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
         }
         HIP_TRY(tmark(b, COS_PHASE_REVERSE, s));
         for (int l = 2 * o.n; l >= 1; --l) {   // reverse
@@ -767,7 +769,8 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
             a.out_bar = d_out_bar;
             a.Gbar_T = GbT;
             a.sbar_T = sbT;
-            HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
+            if (o.sub) HIP_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
+            else HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
         }
     }
     HIP_TRY(tmark(b, COS_PHASE_UNPACK, s));
@@ -784,7 +787,6 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
     if ((st = check_weight(b->flags, cycle_weight))) return st;
     if (!d_out_bar || !d_G_bar) return fail(COS_EINVAL, "d_out_bar and d_G_bar are required");
     if ((b->flags & COS_F_STUBS) && !d_stub_bar) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub_bar is NULL");
-    if (b->flags & COS_F_SUBLATTICE) return fail(COS_EUNSUPPORTED, "the reverse sweep of sublattice batches is not built");
     if ((st = prepare_adjoint(b))) return st;
     hipStream_t s = (hipStream_t)stream;
     for (const OrderGroup &o : b->orders)
@@ -835,8 +837,6 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
     hipStream_t s = (hipStream_t)stream;
     const bool was_timing = b->timing;
     b->timing = false;
-    if (d_out_bar && (b->flags & COS_F_SUBLATTICE))
-        return fail(COS_EUNSUPPORTED, "the reverse sweep of sublattice batches is not built");
     static const int kWaves[] = {4, 8}, kSubWaves[] = {8, 16};
     static const int kCaps[] = {1, 2, 4, 8, 16};
     for (OrderGroup &o : b->orders) {
