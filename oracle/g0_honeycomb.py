@@ -85,3 +85,33 @@ def build_g0(L, t, beta, mu, alpha, delta, cells, tau):
                 assert np.max(np.abs(g.imag)) < 1e-12 * max(1.0, np.max(np.abs(g.real)))
                 G[f, 2 * a:2 * a + 2, 2 * b:2 * b + 2] = g.real
     return G
+
+
+def build_dg0(L, t, beta, mu, alpha, delta, cells, tau):
+    """dG/dxi for a uniform move H -> H + xi of every H(k) (xi = -(mu -
+    alpha)), same shape as :func:`build_g0`.  The eigenvectors do not move, so
+    each eigenvalue's factor f(E) is replaced by its derivative: for a time
+    difference d > 0, f(E) = -exp(-E d)(1 - nF(E)) and f'(E) = f(E)(beta
+    nF(E) - d); for d <= 0, f(E) = exp(-E d) nF(E) and f'(E) = f(E)(beta nF(E)
+    - beta - d)."""
+    mu = np.atleast_1d(np.asarray(mu, dtype=np.float64))
+    alpha = np.atleast_1d(np.asarray(alpha, dtype=np.float64))
+    delta = np.atleast_1d(np.asarray(delta, dtype=np.float64))
+    cells = np.asarray(cells)
+    tau = np.asarray(tau, dtype=np.float64)
+    n = tau.size
+    dG = np.zeros((mu.size, 2 * n, 2 * n))
+    for f in range(mu.size):
+        H, k1, k2 = bloch(L, t, mu[f], alpha[f], delta[f])
+        E, V = np.linalg.eigh(H)
+        nF, _ = _fermi_parts(E, beta)
+        for a in range(n):
+            for b in range(n):
+                d = tau[a] - tau[b]
+                fE = _branch(E, d, beta)
+                dfE = fE * (beta * nF - d) if d > 0 else fE * (beta * nF - beta - d)
+                Gk = np.einsum("xyim,xym,xyjm->xyij", V, dfE, np.conj(V))
+                ph = np.exp(1j * ((cells[a, 0] - cells[b, 0]) * k1 + (cells[a, 1] - cells[b, 1]) * k2))
+                g = np.einsum("xy,xyij->ij", ph, Gk) / (L * L)
+                dG[f, 2 * a:2 * a + 2, 2 * b:2 * b + 2] = g.real
+    return dG

@@ -71,3 +71,20 @@ def test_equal_time_jump():
     want = np.zeros((2, 12))
     want[:, 2:4] = -np.eye(2)        # vertex 1: same cell
     assert np.allclose(jump, want, atol=1e-6)
+
+
+def test_derivative_against_central_differences():
+    """dG/dxi = -dG/dmu: central differences of the propagator in mu
+    (including the equal-time pairs and both signs of the time difference)."""
+    rng = np.random.default_rng(31)
+    n, L, beta = 4, 6, 3.0
+    cells = rng.integers(0, L, size=(n, 2))
+    tau = rng.uniform(0, beta, size=n)
+    tau[2] = tau[1]
+    mu, alpha, delta = np.array([0.3, -0.2]), np.array([0.1, 0.0]), np.array([0.25, -0.25])
+    dG = GH.build_dg0(L, 1.0, beta, mu, alpha, delta, cells, tau)
+    h = 1e-5
+    Gp = GH.build_g0(L, 1.0, beta, mu + h, alpha, delta, cells, tau)
+    Gm = GH.build_g0(L, 1.0, beta, mu - h, alpha, delta, cells, tau)
+    fd = -(Gp - Gm) / (2 * h)
+    assert np.max(np.abs(dG - fd)) <= 1e-8 * max(1.0, np.max(np.abs(fd))), np.max(np.abs(dG - fd))
