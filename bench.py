@@ -114,6 +114,39 @@ def honeycomb_forward(B, torch, reps):
     torch.cuda.synchronize()
     bm.close()
     ref = S / float(2 ** nn)
+    # gradient step: propagators and dG/dxi -> labelled reverse sweep -> chain rule to (mu, alpha)
+    dG = torch.empty_like(G)
+    side = torch.as_tensor(2 * d.n, device=dev)
+    ba = B.Batch(d.n, w.nflav, 1, sublattice=True)
+    ob = torch.ones(n.size, dtype=torch.float64, device=dev)
+    Sg, Gb = torch.empty_like(S), torch.empty_like(G)
+    mub = torch.empty(n.size * w.nflav, dtype=torch.float64, device=dev)
+    alb = torch.empty_like(mub)
+
+    def grad_step():
+        B.build_g0_honeycomb(n.size, dn, dv, dc, dt, w.L, w.t, w.beta, mu, al, st, Goff, G, stream, dG=dG)
+        ba.adjoint(G, Goff, None, -1.0, ob, Sg, Gb, None, stream)
+        B.chain_mu_shift(n.size, side, w.nflav, Goff, Gb, dG, None, 1, 1.0, mub, alb, stream)
+
+    grad_step()
+    ba.autotune(G, Goff, None, -1.0, Sg, ob, Gb, None, stream=stream)
+    grad_step()
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ba.timing(True)
+    a0.record(stream)
+    for _ in range(reps):
+        grad_step()
+    a1.record(stream)
+    torch.cuda.synchronize()
+    aph, _ = ba.timing_read()
+    ba.timing(False)
+    grad = {"configs_per_s": n.size / (a0.elapsed_time(a1) / reps * 1e-3),
+            "ms_per_step": a0.elapsed_time(a1) / reps,
+            "phases_ms": {k: v / reps for k, v in aph.items()},
+            "kernel": "sub_adj_kernel<8, false>", "launch_shape": ba.launch_shape(nn),
+            "S_equals_forward": bool(torch.equal(Sg, S))}
+    ba.close()
     mask_only = {"forward_levels_ms": m0.elapsed_time(m1) / reps,
                  "configs_per_s_forward_levels": n.size / (m0.elapsed_time(m1) / reps * 1e-3),
                  "max_rel_diff_from_labelled_sum": float(((Sm - ref).abs() / ref.abs().clamp_min(1e-300)).max()),
@@ -127,6 +160,7 @@ def honeycomb_forward(B, torch, reps):
             "frac_of_fp64_peak": flop * n.size / (fwd_ms * 1e-3) / PEAK_FP64,
             "state_stream_bytes_per_config": states_bytes,
             "state_stream_TBps": states_bytes * n.size / (fwd_ms * 1e-3) / 1e12,
+            "gradient_step": grad,
             "mask_only_alg1": mask_only,
             "cdet_comparison": cdet}
 

@@ -161,16 +161,21 @@ cos_status cos_build_g0(int32_t nconf, const int32_t *d_n, const int64_t *d_voff
  * d_cells: int32 [sum n][2] unit-cell coordinates in [0, L), 1 <= L <= 32;
  * d_tau [sum n]; d_voff[c]: first vertex of config c; mu, alpha, delta: HOST
  * arrays [nmat].  Output: nmat matrices of side 2 n_c per configuration at
- * d_G[d_Goff[c] + (g*2n_c + i)*2n_c + j].  The equal-time shift the CoS
- * formulation puts on the diagonal is left to the caller. */
+ * d_G[d_Goff[c] + (g*2n_c + i)*2n_c + j].  d_dG (may be NULL) receives, in
+ * the same layout, dG_g/dxi for a uniform move H_g -> H_g + xi (xi = -(mu[g]
+ * - alpha[g]); so d/dmu_g = -d/dxi), for cos_chain_mu_shift.  The equal-time
+ * shift the CoS formulation puts on the diagonal is left to the caller. */
 cos_status cos_build_g0_honeycomb(int32_t nconf, const int32_t *d_n, const int64_t *d_voff,
                                   const int32_t *d_cells, const double *d_tau, int32_t L, double t,
                                   double beta, int32_t nmat, const double *mu, const double *alpha,
-                                  const double *delta, const int64_t *d_Goff, double *d_G, void *stream);
+                                  const double *delta, const int64_t *d_Goff, double *d_G, double *d_dG,
+                                  void *stream);
 
 /* Chain rule to the chemical potential and the shift (Methods: xi = eps -
  * mu + alpha, shift weight sigma = alpha / U).  Per configuration c and
- * matrix g: xb = sum_kj G_bar[g][k][j] * dG[g][k][j];
+ * matrix g: xb = sum_kj G_bar[g][k][j] * dG[g][k][j] over the d_n[c] x d_n[c]
+ * entries of matrix g (d_n[c] is the matrix side: n_c, or 2 n_c for
+ * sublattice matrices);
  *   d_mu_bar[c*nmat + g]    = -xb
  *   d_alpha_bar[c*nmat + g] = +xb + stub_bar[c*nstub + g] / U   (stub_bar may be NULL)
  * For COS_UNIFORM (nmat = 1) the per-flavour shift derivative at equal shifts

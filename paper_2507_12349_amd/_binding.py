@@ -52,7 +52,7 @@ def _load():
         "cos_plan_counts": ([i32, P64, P64, P64, P64, P64, P64], i32),
         "cos_plan_counts_sublattice": ([i32, P64, P64, P64, P64, P64], i32),
         "cos_plan_counts_mask_only": ([i32, i32, P64, P64, P64], i32),
-        "cos_build_g0_honeycomb": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p], i32),
+        "cos_build_g0_honeycomb": ([i32, p, p, p, p, i32, d, d, i32, p, p, p, p, p, p, p], i32),
         "cos_mc_sample": ([i32, i32, i32, d, ctypes.c_uint64, i64, p, p, p], i32),
         "cos_accumulate_moments": ([i32, p, p, p], i32),
         "cos_pade": ([i32, i32, p, d, ctypes.POINTER(d), p], i32),
@@ -223,16 +223,16 @@ def build_g0(nconf, n, voff, sites, tau, L, t, beta, mu, alpha, Goff, G, dG=None
                             _stream(stream)), "cos_build_g0")
 
 
-def build_g0_honeycomb(nconf, n, voff, cells, tau, L, t, beta, mu, alpha, delta, Goff, G, stream=None):
+def build_g0_honeycomb(nconf, n, voff, cells, tau, L, t, beta, mu, alpha, delta, Goff, G, stream=None, dG=None):
     """Device honeycomb propagator builder (2n x 2n matrices, index 2k + s);
-    n, voff, cells, tau, Goff, G are device tensors, mu, alpha, delta host
-    sequences of length nmat."""
+    n, voff, cells, tau, Goff, G (and dG = dG/dxi, optional) are device
+    tensors, mu, alpha, delta host sequences of length nmat."""
     mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
     alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(-1))
     delta = np.ascontiguousarray(np.asarray(delta, dtype=np.float64).reshape(-1))
     _check(lib.cos_build_g0_honeycomb(int(nconf), _ptr(n), _ptr(voff), _ptr(cells), _ptr(tau), int(L), float(t),
                                       float(beta), int(mu.size), _ptr(mu), _ptr(alpha), _ptr(delta), _ptr(Goff),
-                                      _ptr(G), _stream(stream)), "cos_build_g0_honeycomb")
+                                      _ptr(G), _ptr(dG), _stream(stream)), "cos_build_g0_honeycomb")
 
 
 def mc_sample(nconf, n, L, beta, seed, first, sites, tau, stream=None):

@@ -160,7 +160,7 @@ hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int
 hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff, const int32_t *cells,
                                const double *tau, int L, double t, double beta, int nmat, const double *mu,
                                const double *alpha, const double *delta, const int64_t *Goff, double *G,
-                               hipStream_t s);
+                               double *dG, hipStream_t s);
 // CDet comparison path (cos_cdet.hip): workspace elements per configuration
 // (doubles for precision 0, double-double pairs for 1) and the launcher
 int64_t cdet_elems_per_config(int n);

@@ -97,12 +97,19 @@ hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int
 // f(d0 - r)) / 2 * d.sigma / r, so per k two eigenvalues and the unit vector
 // d / r (in LDS) give every sublattice entry.  One workgroup per
 // configuration; thread per vertex pair, four sublattice entries each.
+// dG/dxi for a uniform move H -> H + xi (xi = -(mu - alpha)) shifts both
+// eigenvalues and keeps d / r, so it is the same sum with f replaced by f'.
 // ---------------------------------------------------------------------------
 struct HcParams {
     double mu[COS_FMAX], alpha[COS_FMAX], delta[COS_FMAX];
     double t, beta;
     int L, nmat;
 };
+
+// Fermi function without overflow
+__device__ __forceinline__ double fermi(double x, double beta) {
+    return (x >= 0.0) ? exp(-beta * x) / (1.0 + exp(-beta * x)) : 1.0 / (exp(beta * x) + 1.0);
+}
 
 // imaginary-time factor of one eigenvalue x for the time difference d
 __device__ __forceinline__ double g0_branch(double x, double d, double beta) {
@@ -117,11 +124,13 @@ __global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__rest
                                                            const int32_t *__restrict__ cells,
                                                            const double *__restrict__ tau,
                                                            const int64_t *__restrict__ Goff,
-                                                           double *__restrict__ Gout, const HcParams p) {
+                                                           double *__restrict__ Gout, double *__restrict__ dGout,
+                                                           const HcParams p) {
     extern __shared__ double sm[];
     const int L = p.L, L2 = L * L;
     double *ep = sm, *em = sm + L2, *rz = sm + 2 * L2, *ex = sm + 3 * L2, *ey = sm + 4 * L2;
-    double *cs = sm + 5 * L2, *sn = cs + L;   // cos / sin (2 pi j / L)
+    double *np_ = sm + 5 * L2, *nm_ = sm + 6 * L2;   // Fermi factors of the two eigenvalues
+    double *cs = sm + 7 * L2, *sn = cs + L;   // cos / sin (2 pi j / L)
     const int c = blockIdx.x;
     const int n = nvec[c];
     const int64_t v0 = voff[c];
@@ -141,6 +150,8 @@ __global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__rest
             const double r = sqrt(er * er + ei * ei + dz * dz);
             ep[k] = d0 + r;
             em[k] = d0 - r;
+            np_[k] = fermi(d0 + r, p.beta);
+            nm_[k] = fermi(d0 - r, p.beta);
             const double inv = r > 0.0 ? 1.0 / r : 0.0;   // r = 0: both eigenvalues equal, f(H) = f(d0)
             rz[k] = dz * inv;
             ex[k] = er * inv;
@@ -152,27 +163,40 @@ __global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__rest
             const int r1 = cells[2 * (v0 + a)] - cells[2 * (v0 + b)];
             const int r2 = cells[2 * (v0 + a) + 1] - cells[2 * (v0 + b) + 1];
             const double d = tau[v0 + a] - tau[v0 + b];
-            double aa = 0.0, bb = 0.0, ab = 0.0, ba = 0.0;
+            // d/dx of the branch factor: d > 0: f (beta nF - d); d <= 0: f (beta nF - beta - d)
+            const double dsh = d > 0.0 ? -d : -p.beta - d;
+            double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};   // [G, dG/dxi][aa, bb, ab, ba]
             for (int k = 0; k < L2; ++k) {
                 const int m1 = k % L, m2 = k / L;
                 int ph = (m1 * r1 + m2 * r2) % L;
                 if (ph < 0) ph += L;
-                const double fp = g0_branch(ep[k], d, p.beta), fm = g0_branch(em[k], d, p.beta);
-                const double S = 0.5 * (fp + fm), Dd = 0.5 * (fp - fm);
                 const double c0 = cs[ph], s0 = sn[ph];
-                aa = __builtin_fma(c0, __builtin_fma(Dd, rz[k], S), aa);
-                bb = __builtin_fma(c0, __builtin_fma(-Dd, rz[k], S), bb);
-                // Re[e^{i phi} Dd (ex + i ey)] and Re[e^{i phi} Dd (ex - i ey)]
-                const double xr = Dd * ex[k], xi = Dd * ey[k];
-                ab = __builtin_fma(c0, xr, __builtin_fma(-s0, xi, ab));
-                ba = __builtin_fma(c0, xr, __builtin_fma(s0, xi, ba));
+                const double gp = g0_branch(ep[k], d, p.beta), gm = g0_branch(em[k], d, p.beta);
+                const double fpv[2] = {gp, gp * __builtin_fma(p.beta, np_[k], dsh)};
+                const double fmv[2] = {gm, gm * __builtin_fma(p.beta, nm_[k], dsh)};
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    if (q == 1 && !dGout) break;
+                    const double S = 0.5 * (fpv[q] + fmv[q]), Dd = 0.5 * (fpv[q] - fmv[q]);
+                    acc[q][0] = __builtin_fma(c0, __builtin_fma(Dd, rz[k], S), acc[q][0]);
+                    acc[q][1] = __builtin_fma(c0, __builtin_fma(-Dd, rz[k], S), acc[q][1]);
+                    // Re[e^{i phi} Dd (ex + i ey)] and Re[e^{i phi} Dd (ex - i ey)]
+                    const double xr = Dd * ex[k], xi = Dd * ey[k];
+                    acc[q][2] = __builtin_fma(c0, xr, __builtin_fma(-s0, xi, acc[q][2]));
+                    acc[q][3] = __builtin_fma(c0, xr, __builtin_fma(s0, xi, acc[q][3]));
+                }
             }
             const double inv = 1.0 / (double)L2;
-            double *out = Gout + goff + (int64_t)g * D * D;
-            out[(2 * a) * D + 2 * b] = aa * inv;
-            out[(2 * a) * D + 2 * b + 1] = ab * inv;
-            out[(2 * a + 1) * D + 2 * b] = ba * inv;
-            out[(2 * a + 1) * D + 2 * b + 1] = bb * inv;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                double *base = q == 0 ? Gout : dGout;
+                if (!base) continue;
+                double *out = base + goff + (int64_t)g * D * D;
+                out[(2 * a) * D + 2 * b] = acc[q][0] * inv;
+                out[(2 * a) * D + 2 * b + 1] = acc[q][2] * inv;
+                out[(2 * a + 1) * D + 2 * b] = acc[q][3] * inv;
+                out[(2 * a + 1) * D + 2 * b + 1] = acc[q][1] * inv;
+            }
         }
     }
 }
@@ -180,7 +204,7 @@ __global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__rest
 hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff, const int32_t *cells,
                                const double *tau, int L, double t, double beta, int nmat, const double *mu,
                                const double *alpha, const double *delta, const int64_t *Goff, double *G,
-                               hipStream_t s) {
+                               double *dG, hipStream_t s) {
     HcParams p;
     for (int g = 0; g < COS_FMAX; ++g) {
         p.mu[g] = g < nmat ? mu[g] : 0.0;
@@ -188,8 +212,8 @@ hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff,
         p.delta[g] = g < nmat ? delta[g] : 0.0;
     }
     p.t = t; p.beta = beta; p.L = L; p.nmat = nmat;
-    const size_t shm = (size_t)(5 * L * L + 2 * L) * sizeof(double);
-    hipLaunchKernelGGL(g0_honeycomb_kernel, dim3(nconf), dim3(256), shm, s, n, voff, cells, tau, Goff, G, p);
+    const size_t shm = (size_t)(7 * L * L + 2 * L) * sizeof(double);
+    hipLaunchKernelGGL(g0_honeycomb_kernel, dim3(nconf), dim3(256), shm, s, n, voff, cells, tau, Goff, G, dG, p);
     return hipGetLastError();
 }
 

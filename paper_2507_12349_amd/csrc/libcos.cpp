@@ -963,7 +963,7 @@ cos_status cos_build_g0(int32_t nconf, const int32_t *d_n, const int64_t *d_voff
 cos_status cos_build_g0_honeycomb(int32_t nconf, const int32_t *d_n, const int64_t *d_voff,
                                   const int32_t *d_cells, const double *d_tau, int32_t L, double t, double beta,
                                   int32_t nmat, const double *mu, const double *alpha, const double *delta,
-                                  const int64_t *d_Goff, double *d_G, void *stream) {
+                                  const int64_t *d_Goff, double *d_G, double *d_dG, void *stream) {
     if (nconf < 1) return fail(COS_EINVAL, "nconf must be >= 1");
     if (!d_n || !d_voff || !d_cells || !d_tau || !d_Goff || !d_G || !mu || !alpha || !delta)
         return fail(COS_EINVAL, "null pointer argument");
@@ -971,7 +971,7 @@ cos_status cos_build_g0_honeycomb(int32_t nconf, const int32_t *d_n, const int64
     if (nmat < 1 || nmat > COS_FMAX) return fail(COS_ERANGE, "nmat must be in [1, %d]", COS_FMAX);
     if (!(beta > 0.0)) return fail(COS_ERANGE, "beta must be positive");
     HIP_TRY(launch_g0_honeycomb(nconf, d_n, d_voff, d_cells, d_tau, L, t, beta, nmat, mu, alpha, delta, d_Goff,
-                                d_G, (hipStream_t)stream));
+                                d_G, d_dG, (hipStream_t)stream));
     return COS_OK;
 }
 

@@ -88,3 +88,25 @@ def test_derivative_against_central_differences():
     Gm = GH.build_g0(L, 1.0, beta, mu - h, alpha, delta, cells, tau)
     fd = -(Gp - Gm) / (2 * h)
     assert np.max(np.abs(dG - fd)) <= 1e-8 * max(1.0, np.max(np.abs(fd))), np.max(np.abs(dG - fd))
+
+
+def test_mu_gradient_of_labelled_sum_against_central_differences(oracle_mod):
+    """The chain the GPU test compares with, -sum dS/dG * dG/dxi, against
+    central differences of the labelled sum in mu_f (n = 3, two flavours)."""
+    from oracle import sublattice as SL
+    rng = np.random.default_rng(32)
+    n, L, beta = 3, 5, 2.0
+    cells = rng.integers(0, L, size=(n, 2))
+    tau = rng.uniform(0, beta, size=n)
+    mu, alpha, delta = np.array([0.3, -0.1]), np.array([0.05, -0.05]), np.array([0.2, -0.2])
+    G = GH.build_g0(L, 1.0, beta, mu, alpha, delta, cells, tau)
+    dG = GH.build_dg0(L, 1.0, beta, mu, alpha, delta, cells, tau)
+    _, g = SL.by_assignment_adjoint(G, 2, 1)
+    h = 1e-5
+    for f in range(2):
+        e = np.zeros(2)
+        e[f] = h
+        Sp = SL.by_assignment(GH.build_g0(L, 1.0, beta, mu + e, alpha, delta, cells, tau), 2, 1)
+        Sm = SL.by_assignment(GH.build_g0(L, 1.0, beta, mu - e, alpha, delta, cells, tau), 2, 1)
+        fd = (Sp - Sm) / (2 * h)
+        assert abs(-np.sum(g[f] * dG[f]) - fd) <= 1e-7 * max(1.0, abs(fd)), (f, -np.sum(g[f] * dG[f]), fd)
