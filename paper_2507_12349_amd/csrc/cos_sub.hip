@@ -226,30 +226,41 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
 //   tbar_m = sum_l B(m', h, s_h, l)[(h, s_h)] of the slot the next cycle opens
 //   on (1 at the full mask), B(m, u, s_u)[i] = sum_j G[i][j] a[j] over the
 //   current slots i, and dS/dG[i][j] += f[i] a[j].
-// A wavefront owns whole rows; the dS/dG accumulator of the workgroup's 64
-// configurations sits in LDS ([i][j][lane], 128 KB at n = 8) and is added to
-// the packed gradient once per workgroup and flavour.  G itself is read from
-// LDS when both fit (n <= 6) and from global memory (L2-resident: one
-// group's matrices) above that.
+// A wavefront owns whole rows.  The workgroup keeps the rows i of G it needs
+// and their dS/dG accumulator for its 64 configurations in LDS ([i][j][lane]),
+// adding the accumulator to the packed gradient once per flavour.  Up to
+// n = 6 one workgroup owns every row i (2 x 72 KB at n = 6); at n = 7, 8 the
+// two matrices would not fit (2 x 128 KB at n = 8), so two workgroups share
+// a block of masks, each owning half of the rows i (grid z): both read the
+// child adjoints a, each reads its half of the states and writes its half
+// of B.
 // ---------------------------------------------------------------------------
-template <int N, bool MASK, bool GLDS>
-__device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, const double *__restrict__ Gg, uint32_t gaddr,
-                                            uint32_t gbaddr, const double *__restrict__ F,
-                                            const double *__restrict__ Bn, double *__restrict__ Bc, uint32_t lane8,
-                                            int64_t fpl, int64_t cpl, int64_t npl, int lam, int u, int su, int r,
-                                            bool start, double tb) {
-    constexpr int D = 2 * N;
+template <int N>
+struct SubAdjShape {
+    static constexpr int D = 2 * N;
+    static constexpr bool SPLIT = 2 * D * D * 64 * 8 > 160 * 1024;
+    static constexpr int RI = SPLIT ? N : D;   // rows i owned by one workgroup
+};
+
+template <int N, bool MASK>
+__device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
+                                            const double *__restrict__ F, const double *__restrict__ Bn,
+                                            double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
+                                            int64_t npl, int lam, int u, int su, int r, bool start, double tb,
+                                            int i0) {
+    constexpr int D = 2 * N, RI = SubAdjShape<N>::RI;
     const uint32_t ones = M.ones, twos = M.twos, subb = M.subb;
-    const uint32_t cs = sub_current(N, u, su, ones, twos, subb);
-    const int i0 = cs ? __builtin_ctz(cs) : 0;   // every reachable row has a current slot; guard anyway
-    const double *__restrict__ src = F + lam * fpl + (int64_t)r * D * 64;
+    const uint32_t cs = sub_current(N, u, su, ones, twos, subb) >> i0;   // owned rows, from bit 0
+    if (!(cs & ((1u << RI) - 1u))) return;   // wave-uniform: nothing of this row is owned here
+    const int k0 = __builtin_ctz(cs);
+    const double *__restrict__ src = F + lam * fpl + (int64_t)r * D * 64 + (int64_t)i0 * 64;
     // straight-line loads with selects (unused ones re-read a needed slot)
-    double f[D], a[D];
+    double f[RI], a[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const bool c = (cs >> i) & 1u;
-        const double x = lane_ld(src + (c ? i : i0) * 64, lane8);
-        f[i] = start ? (i == su ? 1.0 : 0.0) : (c ? x : 0.0);   // start: vertex 0 on label s_u
+    for (int k = 0; k < RI; ++k) {
+        const bool c = (cs >> k) & 1u;
+        const double x = lane_ld(src + (c ? k : k0) * 64, lane8);
+        f[k] = start ? (i0 + k == su ? 1.0 : 0.0) : (c ? x : 0.0);   // start: vertex 0 on label s_u
     }
     uint32_t need = 0;   // outputs j with a[j] possibly nonzero (wave-uniform)
 #pragma unroll
@@ -268,41 +279,41 @@ __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, const double *__
         }
     }
     const int jc = 2 * u + su;   // the row's close slot
-    a[jc] += tb;
+#pragma unroll
+    for (int j = 0; j < D; ++j) a[j] = (j == jc) ? a[j] + tb : a[j];
     need |= 1u << jc;
     asm volatile("" : "+v"(gaddr));
     asm volatile("" : "+v"(gbaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
     lds_double *Gb = (lds_double *)(uintptr_t)gbaddr;
-    double *__restrict__ dst = Bc + lam * npl + (int64_t)r * D * 64;
+    double *__restrict__ dst = Bc + lam * npl + (int64_t)r * D * 64 + (int64_t)i0 * 64;
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-        if (!((cs >> i) & 1u)) continue;   // wave-uniform
+    for (int k = 0; k < RI; ++k) {
+        if (!((cs >> k) & 1u)) continue;   // wave-uniform
         double b = 0.0;
 #pragma unroll
         for (int j = 0; j < D; ++j) {
             if (!((need >> j) & 1u)) continue;   // wave-uniform
-            const double g = GLDS ? (double)Gs[(i * D + j) * 64] : lane_ld(Gg + (i * D + j) * 64, lane8);
-            b = __builtin_fma(g, a[j], b);
+            b = __builtin_fma((double)Gs[(k * D + j) * 64], a[j], b);
         }
-        lane_st(dst + i * 64, lane8, b);
+        lane_st(dst + k * 64, lane8, b);
 #pragma unroll
         for (int j = 0; j < D; ++j)
             if ((need >> j) & 1u)   // wave-uniform
-                __hip_atomic_fetch_add(Gb + (i * D + j) * 64, f[i] * a[j], __ATOMIC_RELAXED,
+                __hip_atomic_fetch_add(Gb + (k * D + j) * 64, f[k] * a[j], __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
 template <int N, bool MASK>
 __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
-    constexpr int D = 2 * N;
-    constexpr bool GLDS = 2 * D * D * 64 * 8 <= 160 * 1024;   // G and the accumulator both in LDS
+    constexpr int D = 2 * N, RI = SubAdjShape<N>::RI;
     extern __shared__ double lds[];
-    double *Gb_all = lds;                      // [D * D][64]  dS/dG of the flavour, this workgroup
-    double *Gs_all = lds + D * D * 64;         // [D * D][64]  G of the flavour (GLDS only)
+    double *Gb_all = lds;                      // [RI][D][64]  dS/dG of the owned rows, this workgroup
+    double *Gs_all = lds + RI * D * 64;        // [RI][D][64]  the owned rows of G
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
+    const int i0 = SubAdjShape<N>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
     const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
@@ -321,9 +332,9 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
 
     for (int lam = 0; lam < nfs; ++lam) {
         __syncthreads();   // the previous flavour's accumulator has been flushed
-        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * D * D * 64;
-        for (int i = threadIdx.x; i < D * D * 64; i += blockDim.x) {
-            if (GLDS) Gs_all[i] = gsrc[i];
+        const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * D * D * 64 + (int64_t)i0 * D * 64;
+        for (int i = threadIdx.x; i < RI * D * 64; i += blockDim.x) {
+            Gs_all[i] = gsrc[i];
             Gb_all[i] = 0.0;
         }
         __syncthreads();
@@ -347,8 +358,8 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
             int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
             while (true) {
                 if (!(MASK && u == 0 && ((lam == 0) == full0)))
-                    sub_adj_row<N, MASK, GLDS>(M, gsrc, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, su,
-                                               M.rb + slot, start, tb);
+                    sub_adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, su, M.rb + slot,
+                                         start, tb, i0);
                 ++slot;
                 if (full0 && su == 0) {
                     su = 1;
@@ -361,8 +372,8 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
             }
         }
         __syncthreads();
-        double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64;
-        for (int i = threadIdx.x; i < D * D * 64; i += blockDim.x) {
+        double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64 + (int64_t)i0 * D * 64;
+        for (int i = threadIdx.x; i < RI * D * 64; i += blockDim.x) {
             const double x = Gb_all[i];
             if (x != 0.0) atomicAdd(gb + i, x);
         }
@@ -406,8 +417,9 @@ hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipS
     const int n = a.plan.n;
     const int wpa = adj_waves_per_block();
     const size_t side = 2 * (size_t)n, mat = side * side * 64 * sizeof(double);
-    const size_t shm = (2 * mat <= 160 * 1024) ? 2 * mat : mat;   // G in LDS too when both fit
-    const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups);
+    const bool split = 2 * mat > 160 * 1024;   // as SubAdjShape: two workgroups per block of masks
+    const size_t shm = split ? mat : 2 * mat;   // owned rows of G and of the accumulator
+    const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups, split ? 2u : 1u);
     switch (n) {
 #define COS_SUBADJ_CASE(K)                                                                               \
     case K: {                                                                                            \
