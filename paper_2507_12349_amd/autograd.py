@@ -5,6 +5,8 @@ weights) to the connected sums S_c; its backward runs the reverse sweep kernel
 (forward layers recomputed inside, none stored by autograd).
 ``G0Propagator`` maps per-flavour (mu, alpha) to the propagator matrices of a
 fixed set of vertex configurations; its backward is the chain-rule kernel.
+``HoneycombPropagator`` does the same for the honeycomb lattice (2n x 2n
+matrices for sublattice batches).
 PyTorch only provides device memory, streams and the autograd tape.
 """
 from __future__ import annotations
@@ -68,17 +70,48 @@ class G0Propagator(torch.autograd.Function):
         g = ctx.geom
         mub = torch.empty(g.nconf * ctx.nmat, dtype=torch.float64, device=g.device)
         alb = torch.empty_like(mub)
-        B.chain_mu_shift(g.nconf, g.n, ctx.nmat, g.Goff, gG.contiguous(), dG, None, 1, 1.0, mub, alb)
+        B.chain_mu_shift(g.nconf, g.side, ctx.nmat, g.Goff, gG.contiguous(), dG, None, 1, 1.0, mub, alb)
         # per-configuration contributions -> totals over the batch
         mub = mub.view(g.nconf, ctx.nmat).sum(0).cpu()
         alb = alb.view(g.nconf, ctx.nmat).sum(0).cpu()
         return mub, alb, None
 
 
-class Geometry:
-    """Vertex configurations (sites, times) resident on the GPU."""
+class HoneycombPropagator(torch.autograd.Function):
+    """G = HoneycombPropagator.apply(mu, alpha, delta, geom): per-flavour free
+    propagators of the honeycomb lattice (``geom`` built with
+    ``sublattice=True``; delta: the staggered field, a host sequence, held
+    fixed).  Backward returns dL/dmu, dL/dalpha."""
 
-    def __init__(self, draw, nmat: int, device="cuda"):
+    @staticmethod
+    def forward(ctx, mu, alpha, delta, geom):
+        G = torch.empty(geom.total, dtype=torch.float64, device=geom.device)
+        dG = torch.empty_like(G)
+        B.build_g0_honeycomb(geom.nconf, geom.n, geom.voff, geom.sites, geom.tau, geom.L, geom.t, geom.beta,
+                             mu.detach().cpu().numpy(), alpha.detach().cpu().numpy(),
+                             np.asarray(delta, dtype=np.float64), geom.Goff, G, dG=dG)
+        ctx.geom = geom
+        ctx.nmat = int(mu.numel())
+        ctx.save_for_backward(dG)
+        return G
+
+    @staticmethod
+    def backward(ctx, gG):
+        (dG,) = ctx.saved_tensors
+        g = ctx.geom
+        mub = torch.empty(g.nconf * ctx.nmat, dtype=torch.float64, device=g.device)
+        alb = torch.empty_like(mub)
+        B.chain_mu_shift(g.nconf, g.side, ctx.nmat, g.Goff, gG.contiguous(), dG, None, 1, 1.0, mub, alb)
+        mub = mub.view(g.nconf, ctx.nmat).sum(0).cpu()
+        alb = alb.view(g.nconf, ctx.nmat).sum(0).cpu()
+        return mub, alb, None, None
+
+
+class Geometry:
+    """Vertex configurations (sites or unit cells, times) resident on the GPU.
+    With ``sublattice`` the matrices are 2n x 2n (index 2k + s)."""
+
+    def __init__(self, draw, nmat: int, device="cuda", sublattice: bool = False):
         w = draw.workload
         self.device = torch.device(device)
         self.nconf = int(draw.n.size)
@@ -88,7 +121,9 @@ class Geometry:
         self.voff = torch.as_tensor(draw.voff, device=self.device)
         self.sites = torch.as_tensor(draw.sites, device=self.device).contiguous()
         self.tau = torch.as_tensor(draw.tau, device=self.device)
-        sizes = nmat * draw.n.astype(np.int64) ** 2
+        side = draw.n.astype(np.int64) * (2 if sublattice else 1)
+        self.side = torch.as_tensor(side.astype(np.int32), device=self.device)   # matrix side per config
+        sizes = nmat * side ** 2
         off = np.zeros(self.nconf, dtype=np.int64)
         off[1:] = np.cumsum(sizes[:-1])
         self.Goff_host = off

@@ -81,6 +81,19 @@ class Draw:
         a, b = int(self.voff[c]), int(self.voff[c]) + int(self.n[c])
         return self.sites[a:b], self.tau[a:b]
 
+    def prefix(self, orders):
+        """A draw of len(orders) configurations: configuration c keeps the
+        first orders[c] vertices of this draw's configuration c (small orders
+        on the same lattice and distribution, for references that grow fast
+        with n)."""
+        parts = [self.config(c) for c in range(len(orders))]
+        n = np.asarray(orders, dtype=np.int32)
+        voff = np.zeros(n.size, dtype=np.int64)
+        voff[1:] = np.cumsum(n[:-1])
+        sites = np.concatenate([p[0][:k] for p, k in zip(parts, orders)]).astype(np.int32)
+        tau = np.concatenate([p[1][:k] for p, k in zip(parts, orders)])
+        return Draw(self.workload, n, voff, sites, tau, self.delta)
+
 
 def draw(name: str, nconf: int | None = None) -> Draw:
     """Draw the first ``nconf`` configurations of a workload (all by default).
