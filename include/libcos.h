@@ -129,9 +129,10 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
                                      const double *d_out_bar, double *d_out, double *d_G_bar,
                                      double *d_stub_bar, void *stream);
 
-/* One configuration from HOST buffers (G: nmat*n*n, stub: nstub or NULL when
- * flags lacks COS_F_STUBS); copies to the device, runs the GPU kernel,
- * synchronises and writes *out.  Convenience for small callers and tests. */
+/* One configuration from HOST buffers (G: nmat*n*n, or nmat*(2n)*(2n) with
+ * COS_F_SUBLATTICE; stub: nstub or NULL when flags lacks COS_F_STUBS);
+ * copies to the device, runs the GPU kernel, synchronises and writes *out.
+ * Convenience for small callers and tests. */
 cos_status cos_connected_sum(int32_t n, int32_t nflav, int32_t variant, int32_t flags,
                              const double *G, const double *stub, double cycle_weight,
                              double *out);

@@ -126,11 +126,14 @@ def plan_counts_mask_only(n: int, sublattice: bool = False) -> dict:
     return dict(zip(("states", "ext", "closes"), [v.value for v in vals]))
 
 
-def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=None, w: float = -1.0) -> float:
-    """One configuration from host arrays (the GPU kernel does the work)."""
+def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=None, w: float = -1.0,
+                       sublattice: bool = False, mask_only: bool = False) -> float:
+    """One configuration from host arrays (the GPU kernel does the work);
+    with ``sublattice`` G holds 2n x 2n matrices."""
     G = np.ascontiguousarray(G, dtype=np.float64)
-    n = G.shape[-1]
-    flags = F_STUBS if stub is not None else 0
+    n = G.shape[-1] // 2 if sublattice else G.shape[-1]
+    flags = ((F_STUBS if stub is not None else 0) | (F_SUBLATTICE if sublattice else 0)
+             | (F_MASK_ONLY if mask_only else 0))
     st = None if stub is None else np.ascontiguousarray(stub, dtype=np.float64).reshape(-1)
     out = ctypes.c_double()
     _check(lib.cos_connected_sum(n, nflav, variant, flags, _ptr(G), _ptr(st), float(w), ctypes.byref(out)),

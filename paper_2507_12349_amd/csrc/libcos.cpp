@@ -928,7 +928,8 @@ cos_status cos_connected_sum(int32_t n, int32_t nflav, int32_t variant, int32_t 
     if ((flags & COS_F_STUBS) && !stub) return fail(COS_EINVAL, "COS_F_STUBS set but stub is NULL");
     cos_batch_t b = nullptr;
     if ((st = cos_batch_create(1, &n, nflav, variant, flags, &b))) return st;
-    const size_t ng = (size_t)b->nmat * n * n;
+    const size_t side = (flags & COS_F_SUBLATTICE) ? 2 * (size_t)n : (size_t)n;
+    const size_t ng = (size_t)b->nmat * side * side;
     double *d = nullptr;
     if (hipMalloc((void **)&d, sizeof(double) * (ng + COS_FMAX + 1)) != hipSuccess) {
         cos_batch_destroy(b);

@@ -168,3 +168,20 @@ def test_alg1_su2_block_form(n):
     ref = SL.alg1_brute(A[0], A[1])
     sabs = SL.by_assignment(np.abs(A), 2, 1, 1.0) / 2 ** n
     assert abs(S[0] / 2 ** n - ref) <= 8 * n * (n + 2) * EPS * sabs, (S[0] / 2 ** n, ref)
+
+
+def test_host_entry_point_with_labels():
+    """cos_connected_sum (host buffers, one configuration) with 2n x 2n
+    matrices, plain and mask-only, against the oracle."""
+    from oracle import maskonly as MO
+    from oracle import sublattice as SL
+    from paper_2507_12349_amd import _binding as B
+    announce("sublattice: host entry point, n=3")
+    rng = np.random.default_rng(61)
+    A = rng.normal(size=(2, 6, 6)) * 0.6
+    got = B.connected_sum_host(A, 2, B.FLAVOUR, sublattice=True)
+    ref, sabs = SL.by_assignment(A, 2, 1), SL.by_assignment(np.abs(A), 2, 1, 1.0)
+    assert abs(got - ref) <= 8 * 3 * 5 * EPS * sabs, (got, ref)
+    got_m = B.connected_sum_host(A, 2, B.FLAVOUR, sublattice=True, mask_only=True)
+    ref_m, sabs_m = MO.alg1(A[0], A[1], True), MO.alg1(np.abs(A[0]), np.abs(A[1]), True, w=1.0)
+    assert abs(got_m - ref_m) <= 8 * 3 * 5 * EPS * sabs_m, (got_m, ref_m)
