@@ -209,6 +209,13 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
 /* The launch shape in use for order n (COS_EINVAL if the batch has none). */
 cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves,
                                   int32_t *fwd_masks, int32_t *adj_masks);
+/* Set the launch shape of order n instead of tuning it (for instance one that
+ * cos_batch_autotune found before): fwd_waves in [1, 8] ([1, 16] with
+ * COS_F_SUBLATTICE), fwd_masks and adj_masks in [1, 16] (the forward clamps
+ * its masks per wavefront to 4 with several flavour slots).  COS_EINVAL for
+ * values outside these ranges or an order the batch does not have. */
+cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_waves, int32_t fwd_masks,
+                                      int32_t adj_masks);
 
 /* Phase timing, a measurement aid.  After cos_batch_timing_enable(b, 1),
  * every forward or adjoint call on b records HIP events on its own stream at

@@ -25,7 +25,7 @@ EXPORTED = (
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
-    "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only",
+    "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -64,6 +64,7 @@ def _load():
         "cos_batch_timing_enable": ([p, i32], i32),
         "cos_batch_timing_read": ([p, ctypes.POINTER(d), ctypes.POINTER(i32)], i32),
         "cos_batch_autotune": ([p, p, p, p, d, p, p, p, p, p], i32),
+        "cos_batch_set_launch_shape": ([p, i32, i32, i32, i32], i32),
         "cos_batch_launch_shape": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
@@ -202,6 +203,10 @@ class Batch:
         vals = [ctypes.c_int32() for _ in range(3)]
         _check(lib.cos_batch_launch_shape(self._h, int(n), *[ctypes.byref(v) for v in vals]), "cos_batch_launch_shape")
         return dict(zip(("fwd_waves", "fwd_masks", "adj_masks"), [v.value for v in vals]))
+
+    def set_launch_shape(self, n: int, fwd_waves: int, fwd_masks: int, adj_masks: int):
+        _check(lib.cos_batch_set_launch_shape(self._h, int(n), int(fwd_waves), int(fwd_masks), int(adj_masks)),
+               "cos_batch_set_launch_shape")
 
     def timing(self, enable: bool = True):
         """Record HIP events at the phase boundaries of every later call."""

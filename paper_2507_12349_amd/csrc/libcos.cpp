@@ -797,6 +797,8 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
 }
 
 // device time of fn() on stream s: one warm-up, then the best of `reps`
+// windows; a window repeats fn() back to back until it spans about half a
+// millisecond, so that short calls are not timed at the events' resolution
 static cos_status time_best(hipStream_t s, int reps, const std::function<cos_status()> &fn, float *best) {
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -806,16 +808,22 @@ static cos_status time_best(hipStream_t s, int reps, const std::function<cos_sta
     }
     cos_status st = fn();
     *best = 1e30f;
-    for (int r = 0; r < reps && st == COS_OK; ++r) {
+    int inner = 1;
+    for (int r = 0; r < reps + 1 && st == COS_OK; ++r) {
         float t = 0.0f;
         if (hipEventRecord(e0, s) != hipSuccess) { st = fail(COS_EDEVICE, "hipEventRecord failed"); break; }
-        if ((st = fn())) break;
+        for (int i = 0; i < inner && st == COS_OK; ++i) st = fn();
+        if (st) break;
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
             hipEventElapsedTime(&t, e0, e1) != hipSuccess) {
             st = fail(COS_EDEVICE, "timing events failed");
             break;
         }
-        *best = std::min(*best, t);
+        if (r == 0) {   // sizing window, not counted
+            inner = std::max(1, std::min(64, (int)(0.5f / std::max(t, 1e-3f))));
+            continue;
+        }
+        *best = std::min(*best, t / (float)inner);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
@@ -887,6 +895,23 @@ cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves, 
             if (b->nfs > 1) cap = std::min(cap, kMultiMasks);
             *fwd_masks_cap = cap;
             *adj_masks_cap = o.shape.adj_cap;
+            return COS_OK;
+        }
+    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
+}
+
+cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_waves, int32_t fwd_masks,
+                                      int32_t adj_masks) {
+    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    for (OrderGroup &o : b->orders)
+        if (o.n == n) {
+            const int wmax = o.sub ? 16 : 8;
+            if (fwd_waves < 1 || fwd_waves > wmax) return fail(COS_EINVAL, "fwd_waves must be in [1, %d]", wmax);
+            if (fwd_masks < 1 || fwd_masks > 16 || adj_masks < 1 || adj_masks > 16)
+                return fail(COS_EINVAL, "fwd_masks and adj_masks must be in [1, 16]");
+            o.shape.fwd_wpb = fwd_waves;
+            o.shape.fwd_cap = fwd_masks;
+            o.shape.adj_cap = adj_masks;
             return COS_OK;
         }
     return fail(COS_EINVAL, "the batch has no configuration of order %d", n);

@@ -246,3 +246,32 @@ def test_many_flavours_fit_lds():
     assert np.isfinite(sf) and abs(sf - su) <= 2 * 8 * 10 * 12 * eps * sa, (sf, su, sa)
     bf.close()
     bu.close()
+
+
+def test_set_launch_shape_keeps_sums():
+    """Every launch shape gives the same S bit for bit (each state is written
+    once, every sum in a fixed order); out-of-range shapes are rejected."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("explicit launch shapes, orders 5 and 9, three flavours")
+    rng = np.random.default_rng(23)
+    mats = [rng.normal(size=(3, n, n)) * 0.5 for n in [5] * 70 + [9] * 3]
+    flat, off, n = pack(mats)
+    G, Goff = _dev(flat), _dev(off)
+    b = B.Batch(n, 3, 1)
+    ref = torch.empty(len(mats), dtype=torch.float64, device="cuda:0")
+    b.forward(G, Goff, None, -1.0, ref)
+    for waves, masks in ((1, 1), (4, 16), (8, 2)):
+        for k in (5, 9):
+            b.set_launch_shape(k, waves, masks, 4)
+            assert b.launch_shape(k)["fwd_waves"] == waves
+        out = torch.full_like(ref, float("nan"))
+        b.forward(G, Goff, None, -1.0, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), (waves, masks)
+    for bad in ((0, 4, 4), (9, 4, 4), (8, 0, 4), (8, 4, 17)):
+        with pytest.raises(B.CosError):
+            b.set_launch_shape(5, *bad)
+    with pytest.raises(B.CosError):
+        b.set_launch_shape(6, 8, 4, 4)
+    b.close()
