@@ -462,6 +462,13 @@ def main():
     torch.cuda.synchronize()
     plain_ms = pe0.elapsed_time(pe1)
     plain_equal = bool(torch.equal(Sp, S_batched))
+    # the plain form synchronised after every configuration (host round trip per call)
+    nsync = min(nconf, 256)
+    t0s = time.perf_counter()
+    for c in range(nsync):
+        one.forward(G[int(goff[c]):int(goff[c]) + nn], None, None, -1.0, Sp[c:c + 1], stream)
+        stream.synchronize()
+    plain_sync_rate = nsync / (time.perf_counter() - t0s)
 
     # roofline of the dominant kernel, the reverse level kernel: one launch
     # per level, 2n launches per sweep; algorithmic FLOP of the sweep per
@@ -521,6 +528,7 @@ def main():
         "forward_batched_configs_per_s": nconf / (fwd_ms * 1e-3),
         "forward_kernel_ms": fwd_kernel_ms,
         "forward_plain_configs_per_s": nconf / (plain_ms * 1e-3),
+        "forward_plain_synced_configs_per_s": plain_sync_rate,
         "batched_over_plain": (nconf / (fwd_ms * 1e-3)) / (nconf / (plain_ms * 1e-3)),
         "plain_equals_batched_bitwise": plain_equal,
         "roofline": {"bound": "alu", "kernel": REV_KERNEL % n,
