@@ -310,7 +310,7 @@ def main():
     ap.add_argument("--no-honeycomb", action="store_true", help="skip the sublattice (honeycomb) measurement")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo series measurement")
     ap.add_argument("--no-mask-only", action="store_true", help="skip the SU(2) mask-only comparison")
-    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--cpu-sample", type=int, default=1536)
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
                          "then exit (for rocprofv3 --pmc passes)")
