@@ -195,10 +195,10 @@ cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int6
 /* Autotuner (Results, GPU parallelization: launch shape per problem size).
  * For every order in the batch, times the level kernels over the caller's
  * inputs for each candidate launch shape -- wavefronts per workgroup of the
- * forward kernel (4, 8) and the most masks (state-table tiles) per wavefront
- * (1, 2, 4, 8, 16) of the forward and, when d_out_bar is not NULL, of the
- * reverse kernel -- keeps the fastest per order and uses it for every later
- * call on b.  Arguments as cos_connected_sum_batched / _adjoint; the output
+ * forward kernel (4, 8; 8, 16 with COS_F_SUBLATTICE) and the most masks
+ * (state-table tiles) per wavefront of the forward (1, 2, 4, 8, 16) and, when
+ * d_out_bar is not NULL, of the reverse kernel (1, 2, 4, 6, 7, 8, 10, 12, 16)
+ * -- keeps the fastest per order and uses it for every later call on b.  Arguments as cos_connected_sum_batched / _adjoint; the output
  * buffers are overwritten and on return hold what a call with the chosen
  * shapes writes.  Synchronous (waits for the stream).  S does not depend on
  * the launch shape (bitwise); the gradients do only through the summation

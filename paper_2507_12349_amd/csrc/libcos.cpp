@@ -847,6 +847,7 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
     b->timing = false;
     static const int kWaves[] = {4, 8}, kSubWaves[] = {8, 16};
     static const int kCaps[] = {1, 2, 4, 8, 16};
+    static const int kAdjCaps[] = {1, 2, 4, 6, 7, 8, 10, 12, 16};
     for (OrderGroup &o : b->orders) {
         // forward: waves per workgroup x masks per wavefront
         LaunchShape best = o.shape;
@@ -865,7 +866,7 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
         if (!d_out_bar) continue;
         // reverse: masks per wavefront (the forward part is the same for every candidate)
         tbest = 1e30f;
-        for (int cap : kCaps) {
+        for (int cap : kAdjCaps) {
             o.shape.adj_cap = cap;
             float t;
             st = time_best(s, 3, [&] {
