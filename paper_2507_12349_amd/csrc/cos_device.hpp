@@ -32,6 +32,19 @@ __device__ __forceinline__ double lane_ld(const double *base, uint32_t lane8) {
     asm volatile("" : "+s"(p));
     return *(const __attribute__((address_space(1))) double *)(p + lane8);
 }
+// the same with the nontemporal hint, for DP states: a level writes or reads
+// each state once, and a level's states are far larger than the caches, so
+// they stream past them instead of evicting the tables and matrices
+__device__ __forceinline__ double lane_ld_nt(const double *base, uint32_t lane8) {
+    const global_char *p = (const global_char *)base;
+    asm volatile("" : "+s"(p));
+    return __builtin_nontemporal_load((const __attribute__((address_space(1))) double *)(p + lane8));
+}
+__device__ __forceinline__ void lane_st_nt(double *base, uint32_t lane8, double x) {
+    global_char *p = (global_char *)base;
+    asm volatile("" : "+s"(p));
+    __builtin_nontemporal_store(x, (__attribute__((address_space(1))) double *)(p + lane8));
+}
 __device__ __forceinline__ void lane_st(double *base, uint32_t lane8, double x) {
     global_char *p = (global_char *)base;
     asm volatile("" : "+s"(p));

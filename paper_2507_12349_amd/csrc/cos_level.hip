@@ -125,7 +125,7 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
 #pragma unroll
     for (int v = 0; v < N; ++v) {
         const bool c = (cm >> v) & 1u;
-        f[v] = c ? lane_ld(src + v * 64, lane8) : 0.0;
+        f[v] = c ? lane_ld_nt(src + v * 64, lane8) : 0.0;
     }
     if (start) {
 #pragma unroll
@@ -150,7 +150,7 @@ __device__ __forceinline__ void fwd_row(const MaskRec<N> &M, uint32_t gaddr, con
         }
         const uint32_t ctw = first ? twos : (twos | bit);
         const int crow = M.crb[w] + head_slot(u, ctw);
-        lane_st(nxt + lam * npl + (int64_t)crow * N * 64 + w * 64, lane8, val);
+        lane_st_nt(nxt + lam * npl + (int64_t)crow * N * 64 + w * 64, lane8, val);
     }
 }
 
@@ -298,7 +298,7 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
 #pragma unroll
     for (int v = 0; v < N; ++v) {
         const bool c = (cm >> v) & 1u;
-        const double x = lane_ld(src + (c ? v : v0) * 64, lane8);
+        const double x = lane_ld_nt(src + (c ? v : v0) * 64, lane8);
         f[v] = start ? (v == 0 ? 1.0 : 0.0) : (c ? x : 0.0);   // start: (e_0, 0, 0) = 1
     }
 #pragma unroll
@@ -333,7 +333,7 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
             const double bcv = (v == u) ? a[v] - tb : a[v];
             b = __builtin_fma(-sgx, bcv, b);
         }
-        lane_st(dst + v * 64, lane8, b);
+        lane_st_nt(dst + v * 64, lane8, b);
 #pragma unroll
         for (int w = 0; w < N; ++w)
             if (need & (1u << w))   // wave-uniform

@@ -70,7 +70,7 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
     double f[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) f[i] = ((cs >> i) & 1u) ? lane_ld(src + i * 64, lane8) : 0.0;
+    for (int i = 0; i < D; ++i) f[i] = ((cs >> i) & 1u) ? lane_ld_nt(src + i * 64, lane8) : 0.0;
     if (start) {
 #pragma unroll
         for (int i = 0; i < D; ++i) f[i] = i == su ? 1.0 : 0.0;   // start: vertex 0 on label s_u
@@ -93,7 +93,7 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
             if (!ext) continue;
             if (!(ones & bit)) {
                 const int crow = M.crb[j] + sub_head_slot(u, su, twos);
-                lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + j * 64, lane8, MASK ? a : 2.0 * a);
+                lane_st_nt(nxt + lam * npl + (int64_t)crow * D * 64 + j * 64, lane8, MASK ? a : 2.0 * a);
                 continue;
             }
             const double val = a;
@@ -104,7 +104,7 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
                 continue;
             }
             const int crow = (s ? M.crb[2 * w + 1] : M.crb[2 * w]) + sub_head_slot(u, su, twos | bit);
-            lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * w + s) * 64, lane8, val);
+            lane_st_nt(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * w + s) * 64, lane8, val);
         }
     }
 }
@@ -259,7 +259,7 @@ __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, 
 #pragma unroll
     for (int k = 0; k < RI; ++k) {
         const bool c = (cs >> k) & 1u;
-        const double x = lane_ld(src + (c ? k : k0) * 64, lane8);
+        const double x = lane_ld_nt(src + (c ? k : k0) * 64, lane8);
         f[k] = start ? (i0 + k == su ? 1.0 : 0.0) : (c ? x : 0.0);   // start: vertex 0 on label s_u
     }
     uint32_t need = 0;   // outputs j with a[j] possibly nonzero (wave-uniform)
@@ -296,7 +296,7 @@ __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, 
             if (!((need >> j) & 1u)) continue;   // wave-uniform
             b = __builtin_fma((double)Gs[(k * D + j) * 64], a[j], b);
         }
-        lane_st(dst + k * 64, lane8, b);
+        lane_st_nt(dst + k * 64, lane8, b);
 #pragma unroll
         for (int j = 0; j < D; ++j)
             if ((need >> j) & 1u)   // wave-uniform

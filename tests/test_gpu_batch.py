@@ -208,7 +208,8 @@ def test_autotune_keeps_results():
     b.autotune(G, Goff, st, -1.0, S1, ob, torch.empty_like(G), torch.empty_like(st))
     shapes = {k: b.launch_shape(k) for k in (4, 7, 9)}
     for k, sh in shapes.items():
-        assert sh["fwd_waves"] in (4, 8) and sh["fwd_masks"] in (1, 2, 4, 8, 16) and sh["adj_masks"] in (1, 2, 4, 8, 16), sh
+        assert sh["fwd_waves"] in (4, 8) and sh["fwd_masks"] in (1, 2, 4, 8, 16), sh
+        assert sh["adj_masks"] in (1, 2, 4, 6, 7, 8, 10, 12, 16), sh
     with pytest.raises(B.CosError):
         b.launch_shape(5)
     S2 = torch.full_like(S0, float("nan"))
