@@ -499,9 +499,12 @@ def main():
     if not args.no_cpu:
         threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
         rate, dt = cpu_baseline(d, args.cpu_sample, threads)
+        rate1, dt1 = cpu_baseline(d, 16, 1)
         cpu = {"value": rate, "unit": "configs/s", "cores": threads, "kind": "oracle",
                "sample": "%d configs of the same workload (propagators, float64 DP forward + reverse sweep, "
-                         "chain rule), one config per thread, %.1f s wall" % (args.cpu_sample, dt)}
+                         "chain rule), one config per thread, %.1f s wall" % (args.cpu_sample, dt),
+               "single_core_value": rate1,
+               "single_core_sample": "16 configs on one thread, %.1f s" % dt1}
 
     rec = {
         "metric": "connected-sum configs/sec at n=10 SU(4) FP64 (batched vs plain; fwd+adjoint)",
