@@ -100,7 +100,8 @@ typedef struct cos_batch_s *cos_batch_t;
  * during the call only).  Builds (or reuses) the per-order state tables,
  * uploads the schedule (configurations ordered by decreasing work) and
  * allocates the workspace on the current device.  The handle can then be
- * used for any number of asynchronous calls, including under stream capture.
+ * used for any number of asynchronous calls, including under stream capture,
+ * each made with that same device current (COS_EINVAL otherwise).
  * Returns COS_ERANGE for an order outside [1, COS_NMAX], COS_EINVAL for
  * nconf < 1 or a bad variant / flag. */
 cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
@@ -123,7 +124,10 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
 /* Reverse mode: given d_out_bar[c] = dL/dS_c, writes d_G_bar (layout of d_G)
  * = dL/dG and, with COS_F_STUBS, d_stub_bar (layout of d_stub) = dL/dsigma.
  * The forward pass is recomputed inside; d_out (optional, may be NULL)
- * receives S_c.  Asynchronous on `stream`. */
+ * receives S_c.  Asynchronous on `stream`.  The first reverse call on b (or
+ * cos_batch_autotune with d_out_bar) allocates the reverse-sweep workspace
+ * (every forward level of a chunk of groups); later calls allocate nothing,
+ * so make one call before capturing the adjoint in a graph. */
 cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
                                      const double *d_stub, double cycle_weight,
                                      const double *d_out_bar, double *d_out, double *d_G_bar,
@@ -290,8 +294,9 @@ cos_status cos_cdet_su2(int32_t nconf, int32_t n, const double *d_A, int32_t pre
 /* Diagnostics. */
 const char *cos_status_string(cos_status s);
 const char *cos_last_error(void);
-/* Frees cached state tables of every device.  Outstanding batch handles stay
- * valid only until destroyed; call after all work has completed. */
+/* Frees the cached state tables of every device.  Batch handles point into
+ * these tables, so while any handle is alive nothing is freed and COS_EINVAL
+ * is returned; destroy every handle (after its work has completed) first. */
 cos_status cos_release(void);
 
 #ifdef __cplusplus

@@ -108,6 +108,23 @@ def _stream(stream):
     return getattr(stream, "cuda_stream", stream)
 
 
+def _device_buffer(x, name, dtype, numel):
+    """The kernels address device buffers through raw pointers: a host array,
+    another element type, a strided view or a buffer shorter than the call
+    reads or writes is rejected here, before anything is launched."""
+    if x is None:
+        return
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda):
+        raise TypeError("%s must be a CUDA tensor, got %r" % (name, type(x)))
+    if x.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, x.dtype))
+    if not x.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if x.numel() < numel:
+        raise ValueError("%s holds %d elements, the call needs at least %d" % (name, x.numel(), numel))
+
+
 def plan_counts(n: int) -> dict:
     vals = [ctypes.c_int64() for _ in range(6)]
     _check(lib.cos_plan_counts(int(n), *[ctypes.byref(v) for v in vals]), "cos_plan_counts")
@@ -163,6 +180,24 @@ class Batch:
         _check(lib.cos_batch_create(self.nconf, _ptr(n), self.nflav, self.variant, flags, ctypes.byref(h)),
                "cos_batch_create")
         self._h = h
+        self._total = self.goff()[1]
+
+    def _check_buffers(self, G, Goff, stub, out=None, out_bar=None, G_bar=None, stub_bar=None):
+        """Types and sizes of the device buffers of a call.  With explicit
+        offsets only their count is checked (reading them would synchronise):
+        G must then hold every configuration's matrices at its offset."""
+        import torch
+        f64 = torch.float64
+        if G is None:
+            raise ValueError("G is required")
+        _device_buffer(G, "G", f64, self._total if Goff is None else 1)
+        _device_buffer(Goff, "Goff", torch.int64, self.nconf)
+        ns = self.nconf * self.nstub
+        _device_buffer(stub if self.stubs else None, "stub", f64, ns)
+        _device_buffer(out, "out", f64, self.nconf)
+        _device_buffer(out_bar, "out_bar", f64, self.nconf)
+        _device_buffer(G_bar, "G_bar", f64, G.numel())   # the layout of G
+        _device_buffer(stub_bar if self.stubs else None, "stub_bar", f64, ns)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -184,10 +219,12 @@ class Batch:
         return off, int(sizes.sum())
 
     def forward(self, G, Goff, stub, w, out, stream=None):
+        self._check_buffers(G, Goff, stub, out=out)
         _check(lib.cos_connected_sum_batched(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out),
                                              _stream(stream)), "cos_connected_sum_batched")
 
     def adjoint(self, G, Goff, stub, w, out_bar, out, G_bar, stub_bar, stream=None):
+        self._check_buffers(G, Goff, stub, out=out, out_bar=out_bar, G_bar=G_bar, stub_bar=stub_bar)
         _check(lib.cos_connected_sum_adjoint(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out_bar),
                                              _ptr(out), _ptr(G_bar), _ptr(stub_bar), _stream(stream)),
                "cos_connected_sum_adjoint")
@@ -196,6 +233,7 @@ class Batch:
     def autotune(self, G, Goff, stub, w, out, out_bar=None, G_bar=None, stub_bar=None, stream=None):
         """Pick the fastest launch shape per order on these inputs (synchronous);
         with out_bar the reverse sweep is tuned too."""
+        self._check_buffers(G, Goff, stub, out=out, out_bar=out_bar, G_bar=G_bar, stub_bar=stub_bar)
         _check(lib.cos_batch_autotune(self._h, _ptr(G), _ptr(Goff), _ptr(stub), float(w), _ptr(out_bar), _ptr(out),
                                       _ptr(G_bar), _ptr(stub_bar), _stream(stream)), "cos_batch_autotune")
 

@@ -233,6 +233,7 @@ struct DevTables {
 std::mutex g_mu;
 std::map<std::pair<int, int>, std::shared_ptr<HostPlan>> g_host;   // (n, sublattice)
 std::map<std::tuple<int, int, int>, DevTables> g_dev;              // (device, n, sublattice)
+int64_t g_live = 0;   // batch handles alive: they hold pointers into g_dev's tables
 
 std::shared_ptr<HostPlan> host_plan(int n, bool sub = false) {
     auto key = std::make_pair(n, sub ? 1 : 0);
@@ -362,6 +363,7 @@ struct cos_batch_s {
     bool timing = false;
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_phase;
+    bool counted = false;              // included in g_live
 };
 
 namespace {
@@ -562,6 +564,11 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
         hipMalloc((void **)&b->d_win, sizeof(double) * win) != hipSuccess)
         return fail(COS_ENOMEM, "workspace allocation failed (%.1f MB)", 8.0 * (gt + sg + win) / 1e6);
     HIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nconf, hipMemcpyHostToDevice));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        ++g_live;
+        b->counted = true;
+    }
     *out = b.release();
     return COS_OK;
 }
@@ -577,13 +584,27 @@ cos_status cos_batch_destroy(cos_batch_t b) {
     (void)hipFree(b->d_GbT);
     (void)hipFree(b->d_sbT);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
+    if (b->counted) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        --g_live;
+    }
     delete b;
+    return COS_OK;
+}
+
+// a handle's buffers and tables live on the device it was planned on
+static cos_status check_batch_device(cos_batch_t b) {
+    int cur = -1;
+    HIP_TRY(hipGetDevice(&cur));
+    if (cur != b->dev)
+        return fail(COS_EINVAL, "the batch was planned on device %d but device %d is current", b->dev, cur);
     return COS_OK;
 }
 
 static cos_status check_batch_ptrs(cos_batch_t b, const double *d_G, const int64_t *d_Goff,
                                    const double *d_stub) {
     if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    if (cos_status st = check_batch_device(b)) return st;
     if (!d_G) return fail(COS_EINVAL, "d_G is NULL");
     if (!d_Goff && !b->uniform_n) return fail(COS_EINVAL, "d_Goff is required when the orders differ");
     if ((b->flags & COS_F_STUBS) && !d_stub) return fail(COS_EINVAL, "COS_F_STUBS set but d_stub is NULL");
@@ -1135,6 +1156,9 @@ cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *val
 
 cos_status cos_release(void) {
     std::lock_guard<std::mutex> lk(g_mu);
+    if (g_live > 0)
+        return fail(COS_EINVAL, "%lld batch handle(s) still alive: destroy them before releasing the state tables",
+                    (long long)g_live);
     for (auto &kv : g_dev) {
         int cur = 0;
         (void)hipGetDevice(&cur);

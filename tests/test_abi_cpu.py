@@ -130,3 +130,11 @@ def test_no_gpu_reports_unsupported(B):
     with pytest.raises(B.CosError) as e:
         B.connected_sum_host(np.eye(3), 2)
     assert e.value.status in (-5, -4)
+
+
+def test_release_without_handles(B):
+    """No handle alive: cos_release frees the cached tables (none on a device
+    here) and the next call rebuilds them with the same counts."""
+    before = B.plan_counts(7)
+    assert B.lib.cos_release() == 0
+    assert B.plan_counts(7) == before
