@@ -92,3 +92,25 @@ def test_adjoint_workload_forward(oracle_mod):
     res = gpu_workload(d)
     assert np.all(np.isfinite(res["S"]))
     _check_sample(oracle_mod, d, res, _sample(d, 8, 5))
+
+
+def test_uneven_full(oracle_mod):
+    """All 8192 configurations of the uneven SU(6) shift workload in one batch
+    (orders 6..12, one group of launches per order, the largest orders in
+    chunks of groups): every sum finite; the first 512 bitwise equal to the
+    same configurations run as a batch of their own (a configuration's sum does
+    not depend on the rest of the batch); samples of every order up to 11
+    against the oracle."""
+    announce("workload uneven full (8192 configurations, orders 6..12)")
+    d = draw("uneven")
+    assert d.n.size == 8192 and set(np.unique(d.n)) == set(range(6, 13))
+    res = gpu_workload(d)
+    assert np.all(np.isfinite(res["S"]))
+    head = gpu_workload(draw("uneven", nconf=512))
+    assert np.array_equal(res["S"][:512], head["S"])
+    rng = np.random.default_rng(44)
+    idx = []
+    for k, cnt in ((6, 3), (7, 3), (8, 2), (9, 2), (10, 2), (11, 1)):
+        ok = np.nonzero(d.n[512:] == k)[0] + 512
+        idx += sorted(rng.choice(ok, size=cnt, replace=False).tolist())
+    _check_sample(oracle_mod, d, res, idx)
