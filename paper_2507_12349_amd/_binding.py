@@ -125,6 +125,20 @@ def _device_buffer(x, name, dtype, numel):
         raise ValueError("%s holds %d elements, the call needs at least %d" % (name, x.numel(), numel))
 
 
+def _geometry_buffers(nconf, n, voff, sites, tau, Goff, G, dG):
+    """Buffers of the propagator builders.  Only the per-configuration arrays'
+    lengths are known on the host; the vertex and matrix arrays are checked
+    for type and layout."""
+    import torch
+    _device_buffer(n, "n", torch.int32, nconf)
+    _device_buffer(voff, "voff", torch.int64, nconf)
+    _device_buffer(sites, "sites", torch.int32, 2)
+    _device_buffer(tau, "tau", torch.float64, 1)
+    _device_buffer(Goff, "Goff", torch.int64, nconf)
+    _device_buffer(G, "G", torch.float64, 1)
+    _device_buffer(dG, "dG", torch.float64, G.numel())
+
+
 def plan_counts(n: int) -> dict:
     vals = [ctypes.c_int64() for _ in range(6)]
     _check(lib.cos_plan_counts(int(n), *[ctypes.byref(v) for v in vals]), "cos_plan_counts")
@@ -262,6 +276,7 @@ class Batch:
 def build_g0(nconf, n, voff, sites, tau, L, t, beta, mu, alpha, Goff, G, dG=None, stream=None):
     """Device propagator builder; n, voff, sites, tau, Goff, G, dG are device tensors,
     mu and alpha host sequences of length nmat."""
+    _geometry_buffers(nconf, n, voff, sites, tau, Goff, G, dG)
     mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
     alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(-1))
     _check(lib.cos_build_g0(int(nconf), _ptr(n), _ptr(voff), _ptr(sites), _ptr(tau), int(L), float(t),
@@ -273,6 +288,7 @@ def build_g0_honeycomb(nconf, n, voff, cells, tau, L, t, beta, mu, alpha, delta,
     """Device honeycomb propagator builder (2n x 2n matrices, index 2k + s);
     n, voff, cells, tau, Goff, G (and dG = dG/dxi, optional) are device
     tensors, mu, alpha, delta host sequences of length nmat."""
+    _geometry_buffers(nconf, n, voff, cells, tau, Goff, G, dG)
     mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1))
     alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float64).reshape(-1))
     delta = np.ascontiguousarray(np.asarray(delta, dtype=np.float64).reshape(-1))
@@ -283,12 +299,18 @@ def build_g0_honeycomb(nconf, n, voff, cells, tau, L, t, beta, mu, alpha, delta,
 
 def mc_sample(nconf, n, L, beta, seed, first, sites, tau, stream=None):
     """Device sampler of vertex configurations (vertex 0 at the origin)."""
+    import torch
+    _device_buffer(sites, "sites", torch.int32, 2 * int(nconf) * int(n))
+    _device_buffer(tau, "tau", torch.float64, int(nconf) * int(n))
     _check(lib.cos_mc_sample(int(nconf), int(n), int(L), float(beta), int(seed) & 0xFFFFFFFFFFFFFFFF, int(first),
                              _ptr(sites), _ptr(tau), _stream(stream)), "cos_mc_sample")
 
 
 def accumulate_moments(count, x, acc, stream=None):
     """acc[0] += sum x, acc[1] += sum x^2 (device)."""
+    import torch
+    _device_buffer(x, "x", torch.float64, int(count))
+    _device_buffer(acc, "acc", torch.float64, 2)
     _check(lib.cos_accumulate_moments(int(count), _ptr(x), _ptr(acc), _stream(stream)), "cos_accumulate_moments")
 
 
@@ -308,6 +330,8 @@ def cdet_su2(A, n: int, precision: int, out, eps: float = 1e-12, stream=None):
     allocates its workspace with torch (plumbing) and writes out[nconf]."""
     import torch
     nconf = int(out.numel())
+    _device_buffer(out, "out", torch.float64, nconf)
+    _device_buffer(A, "A", torch.float64, nconf * 2 * (2 * int(n)) ** 2)
     nb = ctypes.c_uint64()
     _check(lib.cos_cdet_workspace(int(n), nconf, int(precision), ctypes.byref(nb)), "cos_cdet_workspace")
     work = torch.empty(int(nb.value), dtype=torch.uint8, device=out.device)
@@ -319,6 +343,16 @@ def cdet_su2(A, n: int, precision: int, out, eps: float = 1e-12, stream=None):
 
 
 def chain_mu_shift(nconf, n, nmat, Goff, G_bar, dG, stub_bar, nstub, U, mu_bar, alpha_bar, stream=None):
+    """Chain rule to mu and alpha per configuration and matrix (device); n
+    holds each configuration's matrix side."""
+    import torch
+    _device_buffer(n, "n", torch.int32, int(nconf))
+    _device_buffer(Goff, "Goff", torch.int64, int(nconf))
+    _device_buffer(G_bar, "G_bar", torch.float64, 1)
+    _device_buffer(dG, "dG", torch.float64, G_bar.numel())
+    _device_buffer(stub_bar, "stub_bar", torch.float64, int(nconf) * int(nstub))
+    _device_buffer(mu_bar, "mu_bar", torch.float64, int(nconf) * int(nmat))
+    _device_buffer(alpha_bar, "alpha_bar", torch.float64, int(nconf) * int(nmat))
     _check(lib.cos_chain_mu_shift(int(nconf), _ptr(n), int(nmat), _ptr(Goff), _ptr(G_bar), _ptr(dG),
                                   _ptr(stub_bar), int(nstub), float(U), _ptr(mu_bar), _ptr(alpha_bar),
                                   _stream(stream)), "cos_chain_mu_shift")

@@ -106,3 +106,43 @@ def test_binding_rejects_bad_buffers():
         assert np.all(out.cpu().numpy() == 0.0)   # zero propagators: S = 0 exactly
     finally:
         b.close()
+
+
+def test_binding_rejects_bad_buffers_of_the_other_entry_points():
+    """Propagator builders, chain rule, sampler, moments and CDet: a host
+    array, another dtype or a buffer shorter than the call needs is rejected
+    before the library is called."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("binding buffer checks: builders, chain rule, sampler, moments, CDet")
+    dev = torch.device("cuda:0")
+    nconf, n = 4, 3
+    nvec = torch.full((nconf,), n, dtype=torch.int32, device=dev)
+    voff = torch.arange(nconf, dtype=torch.int64, device=dev) * n
+    sites = torch.zeros((nconf * n, 2), dtype=torch.int32, device=dev)
+    tau = torch.zeros(nconf * n, dtype=torch.float64, device=dev)
+    Goff = torch.arange(nconf, dtype=torch.int64, device=dev) * (n * n)
+    G = torch.zeros(nconf * n * n, dtype=torch.float64, device=dev)
+    args = dict(n=nvec, voff=voff, sites=sites, tau=tau, Goff=Goff, G=G)
+    for key, bad in (("n", nvec.long()), ("voff", voff[:2]), ("sites", sites.long()), ("tau", tau.float()),
+                     ("Goff", Goff.cpu()), ("G", G.float())):
+        a = dict(args)
+        a[key] = bad
+        with pytest.raises((TypeError, ValueError)):
+            B.build_g0(nconf, a["n"], a["voff"], a["sites"], a["tau"], 4, 1.0, 2.0, [0.0], [0.0], a["Goff"], a["G"])
+    with pytest.raises(ValueError):
+        B.build_g0(nconf, nvec, voff, sites, tau, 4, 1.0, 2.0, [0.0], [0.0], Goff, G, G[:-1].clone())
+    with pytest.raises(ValueError):
+        B.mc_sample(nconf, n, 4, 2.0, 1, 0, sites, tau[:-1])
+    with pytest.raises(ValueError):
+        B.accumulate_moments(nconf, tau[:nconf], torch.zeros(1, dtype=torch.float64, device=dev))
+    mub = torch.zeros(nconf, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        B.chain_mu_shift(nconf, nvec, 1, Goff, G, G.clone(), None, 1, 1.0, mub[:3], mub.clone())
+    with pytest.raises(ValueError):
+        B.cdet_su2(torch.zeros(2 * 4 * 4, dtype=torch.float64, device=dev), 2, 0, torch.zeros(2, dtype=torch.float64, device=dev))
+    # the same buffers, well formed, go through
+    B.build_g0(nconf, nvec, voff, sites, tau, 4, 1.0, 2.0, [0.0], [0.0], Goff, G, torch.empty_like(G))
+    B.mc_sample(nconf, n, 4, 2.0, 1, 0, sites, tau)
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(G.cpu().numpy()))
