@@ -469,6 +469,38 @@ def main():
         one.forward(G[int(goff[c]):int(goff[c]) + nn], None, None, -1.0, Sp[c:c + 1], stream)
         stream.synchronize()
     plain_sync_rate = nsync / (time.perf_counter() - t0s)
+    one.close()
+
+    # the plain form of the adjoint call (forward recomputed + reverse sweep),
+    # one configuration per call, on the first configurations of the batch
+    one_adj = B.Batch([n], w.nflav, 0, stubs=True)
+    nadj = min(nconf, 256)
+    Sa = torch.empty(nadj, dtype=torch.float64, device=dev)
+    Gba = torch.empty(nadj * nn, dtype=torch.float64, device=dev)
+    sba = torch.empty((nadj, 1), dtype=torch.float64, device=dev)
+
+    def adj_plain(c):
+        a0 = int(goff[c])
+        one_adj.adjoint(G[a0:a0 + nn], None, stub[c:c + 1], -1.0, obar[c:c + 1], Sa[c:c + 1],
+                        Gba[c * nn:(c + 1) * nn], sba[c:c + 1], stream)
+
+    for c in range(min(nadj, 8)):
+        adj_plain(c)
+    torch.cuda.synchronize()
+    ae0, ae1 = evpair()
+    ae0.record(stream)
+    for c in range(nadj):
+        adj_plain(c)
+    ae1.record(stream)
+    torch.cuda.synchronize()
+    adj_plain_rate = nadj / (ae0.elapsed_time(ae1) * 1e-3)
+    one_adj.close()
+    # reference: the batched adjoint call on the same inputs
+    batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
+    torch.cuda.synchronize()
+    adj_plain_S_equal = bool(torch.equal(Sa, S[:nadj]))
+    gref = Gb[:nadj * nn]
+    adj_plain_grad_dev = float(((Gba - gref).abs().max() / gref.abs().max()).item())
 
     # roofline of the dominant kernel, the reverse level kernel: one launch
     # per level, 2n launches per sweep; algorithmic FLOP of the sweep per
@@ -534,6 +566,11 @@ def main():
         "forward_plain_synced_configs_per_s": plain_sync_rate,
         "batched_over_plain": (nconf / (fwd_ms * 1e-3)) / (nconf / (plain_ms * 1e-3)),
         "plain_equals_batched_bitwise": plain_equal,
+        "adjoint_batched_configs_per_s": nconf / (acc["adj"] / args.steps * 1e-3),
+        "adjoint_plain_configs_per_s": adj_plain_rate,
+        "adjoint_batched_over_plain": (nconf / (acc["adj"] / args.steps * 1e-3)) / adj_plain_rate,
+        "adjoint_plain_check": {"configs": nadj, "S_equals_batched_bitwise": adj_plain_S_equal,
+                                "max_grad_dev_rel_to_max": adj_plain_grad_dev},
         "roofline": {"bound": "alu", "kernel": REV_KERNEL % n,
                      "unit_of_work": "one launch = one level of the reverse sweep over all %d configs "
                                      "(%d launches per sweep; per-launch figures are sweep averages)" % (nconf, nlaunch),
