@@ -138,3 +138,17 @@ def test_release_without_handles(B):
     before = B.plan_counts(7)
     assert B.lib.cos_release() == 0
     assert B.plan_counts(7) == before
+
+
+def test_device_buffer_check_rejects_host_and_mistyped_buffers(B):
+    """The binding's pre-launch check of a device buffer (host logic): host
+    tensors and arrays, other dtypes, strided views and short buffers are
+    rejected; an absent optional buffer passes."""
+    import torch
+    B._device_buffer(None, "x", torch.float64, 10)
+    with pytest.raises(TypeError):
+        B._device_buffer(torch.zeros(10, dtype=torch.float64), "x", torch.float64, 10)   # host memory
+    with pytest.raises(TypeError):
+        B._device_buffer(np.zeros(10), "x", torch.float64, 10)
+    with pytest.raises(TypeError):
+        B._device_buffer(object(), "x", torch.float64, 1)
