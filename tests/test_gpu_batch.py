@@ -276,3 +276,60 @@ def test_set_launch_shape_keeps_sums():
     with pytest.raises(B.CosError):
         b.set_launch_shape(6, 8, 4, 4)
     b.close()
+
+
+def test_graph_replay_of_the_whole_step():
+    """The benchmark's step (propagators with dG/dxi, adjoint call, chain rule
+    to mu and the shift) captured once; three replays, each after new vertex
+    times are written into the captured buffer (eager work and a
+    synchronisation between replays), against the same step run eagerly:
+    propagators and S bit for bit, the gradients to rounding."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    from paper_2507_12349_amd.autograd import Geometry
+    from paper_2507_12349_amd.workloads import draw
+    announce("graph capture / replay of propagators + adjoint + chain rule (130 x n=8)")
+    dd = draw("adjoint", nconf=130).prefix(np.full(130, 8))   # the first 8 vertices of each configuration
+    w = dd.workload
+    dev = torch.device("cuda:0")
+    geo = Geometry(dd, 1, dev)
+    mu, alpha = np.array(w.mu[:1]), np.zeros(1)
+    nconf = geo.nconf
+    G, dG, Gb = (torch.zeros(geo.total, dtype=torch.float64, device=dev) for _ in range(3))
+    stub = torch.zeros((nconf, 1), dtype=torch.float64, device=dev)
+    sb, S = torch.zeros_like(stub), torch.zeros(nconf, dtype=torch.float64, device=dev)
+    ob = torch.ones(nconf, dtype=torch.float64, device=dev)
+    mub, alb = torch.zeros(nconf, dtype=torch.float64, device=dev), torch.zeros(nconf, dtype=torch.float64, device=dev)
+    b = B.Batch(dd.n, 4, 0, stubs=True)
+
+    def step(st):
+        B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, st)
+        b.adjoint(G, geo.Goff, stub, -1.0, ob, S, Gb, sb, st)
+        B.chain_mu_shift(nconf, geo.n, 1, geo.Goff, Gb, dG, sb, 1, 1.0, mub, alb, st)
+
+    try:
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            step(s)
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            step(s)
+        rng = np.random.default_rng(17)
+        main = torch.cuda.current_stream()
+        for k in range(3):
+            geo.tau.copy_(torch.as_tensor(rng.uniform(0.0, w.beta, size=geo.tau.numel()), device=dev))
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            got = [x.clone() for x in (G, S, Gb, mub, alb)]
+            step(main)
+            torch.cuda.synchronize()
+            assert torch.equal(got[0], G) and torch.equal(got[1], S), k
+            for a, r in zip(got[2:], (Gb, mub, alb)):
+                assert torch.allclose(a, r, rtol=1e-12, atol=1e-13 * float(r.abs().max())), k
+            assert float(S.abs().max()) > 0.0
+    finally:
+        b.close()
