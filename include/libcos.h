@@ -106,6 +106,16 @@ typedef struct cos_batch_s *cos_batch_t;
  * nconf < 1 or a bad variant / flag. */
 cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
                             int32_t variant, int32_t flags, cos_batch_t *out);
+/* Upper bound, in bytes, on each of the two level workspaces of batches
+ * planned from now on in this process (the forward's two level windows, made
+ * at cos_batch_create; the reverse sweep's stored forward levels, made at the
+ * first reverse call).  A batch whose groups of 64 configurations do not all
+ * fit runs them in chunks of as many groups as fit (at least one), one after
+ * the other; results do not depend on the chunking (S bitwise).  0 (the
+ * initial setting) selects a third of the device's memory (96 GB on
+ * MI355X).  COS_EINVAL for bytes < 0.  Batches already planned keep their
+ * bound. */
+cos_status cos_set_workspace_limit(int64_t bytes);
 cos_status cos_batch_destroy(cos_batch_t b);
 
 /* Forward sum for every configuration of the batch, asynchronous on `stream`

@@ -10,7 +10,7 @@ first use: touching any of them without the built library raises ImportError
 _BINDING = {"Batch", "CosError", "connected_sum_host", "plan_counts", "plan_counts_sublattice", "build_g0", "build_g0_honeycomb", "mc_sample",
             "accumulate_moments", "pade", "cdet_su2", "plan_counts_mask_only", "F_MASK_ONLY",
             "chain_mu_shift", "UNIFORM", "FLAVOUR", "F_STUBS", "F_SUBLATTICE", "NMAX", "FMAX", "NMAX_SUBLATTICE",
-            "LIB_PATH", "EXPORTED", "lib"}
+            "LIB_PATH", "EXPORTED", "lib", "set_workspace_limit"}
 
 
 def __getattr__(name):

@@ -25,7 +25,7 @@ EXPORTED = (
     "cos_plan_counts", "cos_status_string", "cos_last_error", "cos_release",
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
-    "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape",
+    "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape", "cos_set_workspace_limit",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -61,6 +61,7 @@ def _load():
         "cos_status_string": ([i32], ctypes.c_char_p),
         "cos_last_error": ([], ctypes.c_char_p),
         "cos_release": ([], i32),
+        "cos_set_workspace_limit": ([i64], i32),
         "cos_batch_timing_enable": ([p, i32], i32),
         "cos_batch_timing_read": ([p, ctypes.POINTER(d), ctypes.POINTER(i32)], i32),
         "cos_batch_autotune": ([p, p, p, p, d, p, p, p, p, p], i32),
@@ -137,6 +138,12 @@ def _geometry_buffers(nconf, n, voff, sites, tau, Goff, G, dG):
     _device_buffer(Goff, "Goff", torch.int64, nconf)
     _device_buffer(G, "G", torch.float64, 1)
     _device_buffer(dG, "dG", torch.float64, G.numel())
+
+
+def set_workspace_limit(nbytes: int):
+    """Bound each level workspace of batches planned from now on (0: a third
+    of the device memory)."""
+    _check(lib.cos_set_workspace_limit(int(nbytes)), "cos_set_workspace_limit")
 
 
 def plan_counts(n: int) -> dict:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <complex>
@@ -248,9 +249,10 @@ std::shared_ptr<HostPlan> host_plan(int n, bool sub = false) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// upper bound on a batch's workspace (bytes); larger orders get fewer
-// concurrent workgroups instead of more memory
-constexpr int64_t kWorkspaceCap = (int64_t)24 << 30;
+// upper bound on each of a batch's two level workspaces (bytes), fixed when
+// the batch is planned: cos_set_workspace_limit, or by default a third of the
+// device's memory.  A batch whose groups do not fit runs them in chunks.
+std::atomic<int64_t> g_ws_limit{0};
 
 cos_status device_plan(int dev, int n, bool sub, DevPlan *out) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -284,7 +286,7 @@ cos_status device_plan(int dev, int n, bool sub, DevPlan *out) {
     return COS_OK;
 }
 
-cos_status check_device(int *dev, int *ncu) {
+cos_status check_device(int *dev, int *ncu, int64_t *mem = nullptr) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count < 1)
         return fail(COS_EUNSUPPORTED, "no HIP device available");
@@ -294,6 +296,7 @@ cos_status check_device(int *dev, int *ncu) {
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
         return fail(COS_EUNSUPPORTED, "device %d is %s; this library is built for gfx950", *dev, prop.gcnArchName);
     *ncu = prop.multiProcessorCount;
+    if (mem) *mem = (int64_t)prop.totalGlobalMem;
     return COS_OK;
 }
 
@@ -345,6 +348,7 @@ struct OrderGroup {
 
 struct cos_batch_s {
     int dev = 0, ncu = 0;
+    int64_t ws_cap = 0;                // bytes per level workspace (chunking of the groups)
     int32_t nconf = 0, nflav = 0, variant = 0, flags = 0;
     int nfs = 1, nmat = 1, nstub = 1;
     bool uniform_n = true;
@@ -503,12 +507,14 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
         if (n[c] < 1 || n[c] > nmax)
             return fail(COS_ERANGE, "n[%d] = %d outside [1, %d]", c, n[c], nmax);
     int dev = 0, ncu = 0;
-    if ((st = check_device(&dev, &ncu))) return st;
+    int64_t mem = 0;
+    if ((st = check_device(&dev, &ncu, &mem))) return st;
 
     struct Del { void operator()(cos_batch_s *p) const { cos_batch_destroy(p); } };
     std::unique_ptr<cos_batch_s, Del> b(new cos_batch_s());
     b->dev = dev;
     b->ncu = ncu;
+    b->ws_cap = g_ws_limit.load() > 0 ? g_ws_limit.load() : mem / 3;
     b->nconf = nconf;
     b->nflav = nflav;
     b->variant = variant;
@@ -548,7 +554,7 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
         }
         const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
         const int64_t per_group = 2 * (int64_t)o.hp->max_rows * rs;
-        o.chunk_fwd = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
+        o.chunk_fwd = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, b->ws_cap / (8 * per_group)));
         win = std::max(win, per_group * o.chunk_fwd);
         gt += (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
         sg += (int64_t)o.ngroups * b->nfs * 64;
@@ -715,7 +721,7 @@ static cos_status prepare_adjoint(cos_batch_t b) {
         const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
         // all forward levels and two adjoint windows
         const int64_t per_group = ((int64_t)o.hp->rows.size() + 2 * (int64_t)o.hp->max_rows) * rs;
-        o.chunk_adj = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, kWorkspaceCap / (8 * per_group)));
+        o.chunk_adj = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, b->ws_cap / (8 * per_group)));
         fall = std::max(fall, per_group * o.chunk_adj);
         o.gb_off = gb;
         o.sb_off = sb;
@@ -1151,6 +1157,12 @@ cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *val
             ac[j] = a[j];
         }
     }
+    return COS_OK;
+}
+
+cos_status cos_set_workspace_limit(int64_t bytes) {
+    if (bytes < 0) return fail(COS_EINVAL, "bytes must be >= 0, got %lld", (long long)bytes);
+    g_ws_limit.store(bytes);
     return COS_OK;
 }
 

@@ -152,3 +152,11 @@ def test_device_buffer_check_rejects_host_and_mistyped_buffers(B):
         B._device_buffer(np.zeros(10), "x", torch.float64, 10)
     with pytest.raises(TypeError):
         B._device_buffer(object(), "x", torch.float64, 1)
+
+
+def test_workspace_limit_arguments(B):
+    """Host-side argument check of the workspace bound (no device needed)."""
+    with pytest.raises(B.CosError):
+        B.set_workspace_limit(-1)
+    B.set_workspace_limit(1 << 30)
+    B.set_workspace_limit(0)   # back to the default
