@@ -143,6 +143,32 @@ cos_status cos_connected_sum_adjoint(cos_batch_t b, const double *d_G, const int
                                      const double *d_out_bar, double *d_out, double *d_G_bar,
                                      double *d_stub_bar, void *stream);
 
+/* For callers that cannot allocate device memory -- code under stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the forward
+ * sums of cos_connected_sum_batched for nconf configurations of one order n
+ * (1 <= n <= COS_STATIC_NMAX) stored back to back (d_G holds nconf blocks of
+ * nmat*n*n doubles, nmat = 1 for COS_UNIFORM and nflav otherwise; d_stub
+ * nconf blocks of nstub weights, required iff flags = COS_F_STUBS, the only
+ * flag taken), with no batch handle.  Writes d_out[c] = S_c, the same values
+ * as the batched call (same kernels).  Every workspace lives in one static
+ * device array of COS_STATIC_SCRATCH_BYTES per device, which each device the
+ * library runs on holds until the process ends: its state tables for orders
+ * 1..COS_STATIC_NMAX, then the call's schedule, packed inputs and two level
+ * windows (a call processes its groups of 64 configurations in chunks of as
+ * many as fit).  A call that needs more than the array holds (too many
+ * configurations or flavour slots for the packed inputs plus one group's
+ * windows) returns COS_ERANGE with the sizes in cos_last_error.  The first
+ * call on a device takes the array's address and uploads the tables
+ * (synchronous, not capturable); later calls only queue kernels on `stream`
+ * and can be captured in a graph.  No call allocates device memory.  All
+ * calls on one device share the array, so calls that overlap on one device
+ * (another stream, another thread) race: serialise them. */
+#define COS_STATIC_NMAX 8
+#define COS_STATIC_SCRATCH_BYTES (64 << 20)
+cos_status cos_connected_sum_static(int32_t nconf, int32_t n, int32_t nflav, int32_t variant, int32_t flags,
+                                    const double *d_G, const double *d_stub, double cycle_weight,
+                                    double *d_out, void *stream);
+
 /* One configuration from HOST buffers (G: nmat*n*n, or nmat*(2n)*(2n) with
  * COS_F_SUBLATTICE; stub: nstub or NULL when flags lacks COS_F_STUBS);
  * copies to the device, runs the GPU kernel, synchronises and writes *out.

@@ -26,6 +26,7 @@ EXPORTED = (
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
     "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape", "cos_set_workspace_limit",
+    "cos_connected_sum_static",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -66,6 +67,7 @@ def _load():
         "cos_batch_timing_read": ([p, ctypes.POINTER(d), ctypes.POINTER(i32)], i32),
         "cos_batch_autotune": ([p, p, p, p, d, p, p, p, p, p], i32),
         "cos_batch_set_launch_shape": ([p, i32, i32, i32, i32], i32),
+        "cos_connected_sum_static": ([i32, i32, i32, i32, i32, p, p, d, p, p], i32),
         "cos_batch_launch_shape": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
@@ -178,6 +180,26 @@ def connected_sum_host(G: np.ndarray, nflav: int, variant: int = UNIFORM, stub=N
     _check(lib.cos_connected_sum(n, nflav, variant, flags, _ptr(G), _ptr(st), float(w), ctypes.byref(out)),
            "cos_connected_sum")
     return out.value
+
+
+STATIC_NMAX = 8
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def connected_sum_static(G, n: int, nflav: int, variant: int, stub, w: float, out, stream=None):
+    """Forward sums of out.numel() configurations of order n stored back to
+    back in G, through the entry point that allocates no device memory (its
+    workspace is the library's static device array, shared by every call on a
+    device: calls must not overlap)."""
+    import torch
+    nconf = int(out.numel())
+    nmat = int(nflav) if variant == FLAVOUR else 1
+    _device_buffer(G, "G", torch.float64, nconf * nmat * int(n) * int(n))
+    _device_buffer(stub, "stub", torch.float64, nconf * nmat)
+    _device_buffer(out, "out", torch.float64, nconf)
+    _check(lib.cos_connected_sum_static(nconf, int(n), int(nflav), int(variant), F_STUBS if stub is not None else 0,
+                                        _ptr(G), _ptr(stub), float(w), _ptr(out), _stream(stream)),
+           "cos_connected_sum_static")
 
 
 class Batch:

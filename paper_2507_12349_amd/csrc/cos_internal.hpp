@@ -173,5 +173,46 @@ hipError_t launch_moments(int count, const double *x, double *acc, hipStream_t s
 hipError_t launch_chain(int nconf, const int32_t *n, int nmat, const int64_t *Goff, const double *Gb,
                         const double *dG, const double *sb, int nstub, double U, double *mub,
                         double *alb, hipStream_t s);
+// p[i] = i for i < n (the identity schedule of a one-order batch)
+hipError_t launch_iota(int32_t *p, int n, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Forward sums on device memory the caller places (libcos.cpp), for the entry
+// point that allocates nothing (cos_static.hip).
+// ---------------------------------------------------------------------------
+// records the error text of the calling thread (cos_last_error) and returns s
+cos_status report(cos_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+// gfx950 check and compute-unit count of the current device
+cos_status current_device(int *dev, int *ncu);
+// host state tables of order n (built once, cached for the process)
+struct PlanTables {
+    const int32_t *mrec;      // [masks][kRecInts]
+    size_t mrec_ints;
+    const int4 *levels;       // [2n + 2]
+    size_t nlevels;
+    int32_t max_rows, max_masks;
+    int64_t total_rows;
+};
+cos_status plan_tables(int n, PlanTables *out);
+// workspace of one forward call: every pointer inside device memory the
+// caller owns; the level windows hold `chunk` groups of 64 configurations
+struct FixedWorkspace {
+    DevPlan plan;             // state tables of the order, already on the device
+    int32_t *order;           // [nconf]
+    double *GT, *sigT;        // packed propagators and shift weights of every group
+    int32_t *lane;            // [ngroups * 64]
+    double *win;              // two level windows of `chunk` groups
+    int32_t chunk;
+};
+// sizes (doubles, or int32 for order / lane) of the pieces of a FixedWorkspace
+struct FixedSizes {
+    int64_t order_ints, gt_doubles, sig_doubles, lane_ints, win_doubles_per_group;
+};
+FixedSizes fixed_sizes(int nconf, int n, int nfs, int32_t max_rows);
+// forward sums of nconf configurations of order n stored back to back (layout
+// of cos_connected_sum_batched with d_Goff = NULL), asynchronous on s
+cos_status forward_fixed(int dev, int ncu, const FixedWorkspace &ws, int32_t nconf, int32_t n, int32_t nflav,
+                         int32_t variant, int32_t flags, const double *d_G, const double *d_stub,
+                         double cycle_weight, double *d_out, hipStream_t s);
 
 }  // namespace libcos

@@ -417,6 +417,11 @@ __global__ void zero_kernel(double *p, int64_t n) {
     if (i < n) p[i] = 0.0;
 }
 
+__global__ void iota_kernel(int32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = i;
+}
+
 // packed gradients -> caller layout
 __global__ void unpack_kernel(const PackArgs A, const double *__restrict__ GbT, const double *__restrict__ sbT,
                               double *__restrict__ Gb, double *__restrict__ sb) {
@@ -454,6 +459,12 @@ hipError_t launch_unpack(const PackArgs &a, const double *GbT, const double *sbT
 hipError_t launch_zero(double *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota(int32_t *p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(iota_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
     return hipGetLastError();
 }
 

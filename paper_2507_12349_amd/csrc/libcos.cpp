@@ -1184,3 +1184,80 @@ cos_status cos_release(void) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Forward sums on workspace the caller places (the allocation-free entry
+// point in cos_static.hip builds on these).
+// ---------------------------------------------------------------------------
+cos_status libcos::report(cos_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+cos_status libcos::current_device(int *dev, int *ncu) { return check_device(dev, ncu); }
+
+cos_status libcos::plan_tables(int n, PlanTables *out) {
+    if (n < 1 || n > COS_NMAX) return fail(COS_ERANGE, "n must be in [1, %d], got %d", COS_NMAX, n);
+    std::shared_ptr<HostPlan> p;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        p = host_plan(n);
+    }
+    // the plan stays in the process-wide cache, which only cos_release clears
+    out->mrec = p->mrec.data();
+    out->mrec_ints = p->mrec.size();
+    out->levels = p->levels.data();
+    out->nlevels = p->levels.size();
+    out->max_rows = p->max_rows;
+    out->max_masks = p->max_masks;
+    out->total_rows = (int64_t)p->rows.size();
+    return COS_OK;
+}
+
+FixedSizes libcos::fixed_sizes(int nconf, int n, int nfs, int32_t max_rows) {
+    const int64_t ngroups = (nconf + 63) / 64;
+    FixedSizes z;
+    z.order_ints = nconf;
+    z.gt_doubles = ngroups * nfs * n * n * 64;
+    z.sig_doubles = ngroups * nfs * 64;
+    z.lane_ints = ngroups * 64;
+    z.win_doubles_per_group = 2 * (int64_t)max_rows * nfs * n * 64;
+    return z;
+}
+
+cos_status libcos::forward_fixed(int dev, int ncu, const FixedWorkspace &ws, int32_t nconf, int32_t n,
+                                 int32_t nflav, int32_t variant, int32_t flags, const double *d_G,
+                                 const double *d_stub, double cycle_weight, double *d_out, hipStream_t s) {
+    // a batch description on the stack: every device pointer is the caller's
+    cos_batch_s b;
+    b.dev = dev;
+    b.ncu = ncu;
+    b.nconf = nconf;
+    b.nflav = nflav;
+    b.variant = variant;
+    b.flags = flags;
+    b.nfs = b.nmat = b.nstub = variant == COS_FLAVOUR ? nflav : 1;
+    b.uniform_n = true;
+    b.plans[n] = ws.plan;
+    b.d_order = ws.order;
+    b.d_GT = ws.GT;
+    b.d_sigT = ws.sigT;
+    b.d_lane = ws.lane;
+    b.d_win = ws.win;
+    OrderGroup o;
+    o.n = n;
+    o.count = nconf;
+    o.ngroups = (nconf + 63) / 64;
+    o.chunk_fwd = std::max(1, std::min(ws.chunk, o.ngroups));
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        o.hp = host_plan(n);
+    }
+    HIP_TRY(launch_iota(ws.order, nconf, s));
+    return forward_order(&b, o, d_G, nullptr, d_stub, cycle_weight, d_out, s);
+}

@@ -112,6 +112,18 @@ def test_argument_validation_without_device(B):
     assert lib.cos_batch_timing_enable(None, 1) == -1
     ms = (ctypes.c_double * 4)()
     assert lib.cos_batch_timing_read(None, ms, None) == -1
+    # the allocation-free forward: every argument checked before the device is touched
+    st = lib.cos_connected_sum_static
+    assert st(0, 4, 2, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -1      # nconf
+    assert st(4, 9, 2, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -2      # above its orders
+    assert st(4, 0, 2, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -2
+    assert st(4, 4, 0, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -2      # nflav
+    assert st(4, 4, 2, 2, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -1      # variant
+    assert st(4, 4, 2, 1, 2, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -1      # sublattice flag
+    assert st(4, 4, 2, 1, 1, G.ctypes.data, None, -1.0, G.ctypes.data, None) == -1      # shifts without weights
+    assert st(4, 4, 2, 1, 0, None, None, -1.0, G.ctypes.data, None) == -1
+    assert "orders 1..8" in (st(4, 9, 2, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None),
+                             lib.cos_last_error().decode())[1]
     assert _st(B, 0) == "ok" and _st(B, -2) == "argument out of range"
 
 
