@@ -274,6 +274,220 @@ def mc_series(torch, orders=8, nconf=8192, nbatches=4):
             "pade_of_correction_at_xi_1": pade}
 
 
+def _flop_per_config(B, n, nflav, variant, stubs):
+    """Algorithmic FLOP of one forward sum (2 per FMA): every extension and
+    close transition once per flavour slot, plus the shift-head transitions."""
+    pc = B.plan_counts(int(n))
+    nfs = nflav if variant == 1 else 1
+    return 2.0 * nfs * (pc["ext"] + pc["closes"]) + (2.0 * nfs * pc["stub_edges"] if stubs else 0.0)
+
+
+def _refs_stats(name, S_host, idx_all=None):
+    """Deviation of sums computed on the GPU's own propagators from the
+    oracle's references (tests/golden/refs_NAME.npz, long double DP on the
+    oracle's propagators; the two propagator builds differ in the last bits,
+    so this is a consistency figure, not the parity gate of the tests) and the
+    cancellation kappa = S_abs / |S| of the referenced configurations."""
+    path = os.path.join(ROOT, "tests", "golden", "refs_%s.npz" % name)
+    if not os.path.exists(path):
+        return None
+    r = np.load(path)
+    idx = r["idx"]
+    rel = np.abs(S_host[idx] - r["S"]) / np.abs(r["S"])
+    kappa = r["S_abs"] / np.abs(r["S"])
+    low = kappa <= 1e5
+    return {"configs": int(idx.size), "rel_dev_median": float(np.median(rel)),
+            "rel_dev_max_kappa_le_1e5": float(rel[low].max()) if low.any() else None,
+            "rel_dev_max": float(rel.max()),
+            "kappa_median": float(np.median(kappa)), "kappa_p90": float(np.quantile(kappa, 0.9)),
+            "kappa_max": float(kappa.max()), "configs_kappa_gt_1e5": int((~low).sum())}
+
+
+def _cpu_forward_rate(d, idx, threads, variant, nflav, stubs_of):
+    """Oracle DP (float64) forward sums of configurations idx, one per thread:
+    configurations per second and wall time."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from oracle import g0
+    w = d.workload
+    oracle.build(force=False)
+    mats = {}
+    for c in idx:
+        sites, tau = d.config(c)
+        nmat = nflav if variant == 1 else 1
+        alpha = np.asarray(d.delta[:nmat]) if variant == 1 else np.zeros(1)
+        G, _ = g0.build_g0(w.L, w.t, w.beta, np.asarray(w.mu[:nmat]), alpha, sites, tau)
+        mats[c] = G[0] if variant == 0 else G
+
+    def one(c):
+        return oracle.dp(mats[c], nflav, variant, stubs_of(c), -1.0, precision="d")
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, idx))
+    dt = time.perf_counter() - t0
+    return len(idx) / dt, dt
+
+
+def workload_legs(B, torch, reps, cpu_threads=0):
+    """The other workloads of the measurement plan, forward sums on the GPU
+    with inputs resident (propagator kernel + batched levels), autotuned:
+      plain_single  (4x4, beta=2, SU(2), n=4, 1 config): plain call latency
+      plain_batch   (8x8, beta=4, SU(4), n=8, 4096): batched vs one call per config
+      sym_broken    (8x8, beta=4, SU(3) flavour mu, n=10, 1024)
+      uneven        (16x16, beta=5, SU(6) shifts, n=6..12, 8192): graph replay
+    each with configs/s, algorithmic FP64 TFLOP/s against the 78.6 TFLOP/s
+    peak, the deviation from the oracle's references and their kappa; with
+    cpu_threads the oracle's forward on a small sample beside it."""
+    from paper_2507_12349_amd.autograd import Geometry
+    from paper_2507_12349_amd.workloads import draw
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    for name in ("plain_single", "plain_batch", "sym_broken", "uneven"):
+        d = draw(name)
+        w = d.workload
+        nmat = w.nflav if w.variant == 1 else 1
+        mu = np.asarray(w.mu[:nmat])
+        alpha = np.asarray(d.delta[:nmat]) if w.variant == 1 else np.zeros(1)
+        geo = Geometry(d, nmat, dev)
+        nconf = geo.nconf
+        G = torch.empty(geo.total, dtype=torch.float64, device=dev)
+        st = None
+        if w.stubs:
+            st = torch.as_tensor(np.tile(d.delta[:nmat] / w.U, (nconf, 1)), device=dev)
+        b = B.Batch(d.n, w.nflav, w.variant, stubs=st is not None)
+        S = torch.empty(nconf, dtype=torch.float64, device=dev)
+
+        def g0(s=stream):
+            B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, None, s)
+
+        g0()
+        b.autotune(G, geo.Goff, st, -1.0, S, stream=stream)
+        fpc = {int(k): _flop_per_config(B, k, w.nflav, w.variant, st is not None) for k in np.unique(d.n)}
+        flop = float(sum(fpc[int(k)] * int((d.n == k).sum()) for k in fpc))
+        leg = {"workload": w.note, "nconf": nconf}
+        if name == "uneven":
+            # the whole step (propagators + every order's level launches) replayed from one graph
+            cs = torch.cuda.Stream()
+            cs.wait_stream(stream)
+            with torch.cuda.stream(cs):
+                g0(cs)
+                b.forward(G, geo.Goff, st, -1.0, S, cs)
+            stream.wait_stream(cs)
+            torch.cuda.synchronize()
+            graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(graph, stream=cs):
+                g0(cs)
+                b.forward(G, geo.Goff, st, -1.0, S, cs)
+            graph.replay()
+            torch.cuda.synchronize()
+            e0, e1 = ev()
+            e0.record(stream)
+            for _ in range(reps):
+                graph.replay()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            leg["graph_replay"] = True
+            leg["orders"] = {int(k): int((d.n == k).sum()) for k in np.unique(d.n)}
+        else:
+            g0()
+            b.forward(G, geo.Goff, st, -1.0, S, stream)
+            torch.cuda.synchronize()
+            e0, e1 = ev()
+            e0.record(stream)
+            for _ in range(reps):
+                g0()
+                b.forward(G, geo.Goff, st, -1.0, S, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+        # the level launches alone (phase events on the launch stream)
+        b.timing(True)
+        for _ in range(reps):
+            b.forward(G, geo.Goff, st, -1.0, S, stream)
+        ph, _ = b.timing_read()
+        b.timing(False)
+        lv_ms = ph["forward"] / reps
+        leg.update({"configs_per_s": nconf / (ms * 1e-3), "ms_per_batch_incl_g0": ms, "forward_levels_ms": lv_ms,
+                    "flop_per_config_mean": flop / nconf, "forward_tflops": flop / (lv_ms * 1e-3) / 1e12,
+                    "frac_of_fp64_peak": flop / (lv_ms * 1e-3) / PEAK_FP64,
+                    "launch_shapes": {int(k): b.launch_shape(int(k)) for k in np.unique(d.n)}})
+        S_host = S.cpu().numpy()
+        if name in ("plain_single", "plain_batch"):
+            # the plain form: one call per configuration (2n level launches, one of 64 lanes busy)
+            n0 = int(d.n[0])
+            one = B.Batch([n0], w.nflav, w.variant)
+            Sp = torch.empty_like(S)
+            nn = nmat * n0 * n0
+            goff = geo.Goff_host
+            for c in range(min(nconf, 16)):
+                one.forward(G[int(goff[c]):int(goff[c]) + nn], None, None, -1.0, Sp[c:c + 1], stream)
+            torch.cuda.synchronize()
+            npl = nconf if nconf > 1 else 200
+            p0, p1 = ev()
+            p0.record(stream)
+            for i in range(npl):
+                c = i % nconf
+                one.forward(G[int(goff[c]):int(goff[c]) + nn], None, None, -1.0, Sp[c:c + 1], stream)
+            p1.record(stream)
+            torch.cuda.synchronize()
+            one.close()
+            plain = npl / (p0.elapsed_time(p1) * 1e-3)
+            leg.update({"plain_configs_per_s": plain, "batched_over_plain": leg["configs_per_s"] / plain,
+                        "plain_equals_batched_bitwise": bool(torch.equal(Sp, S)),
+                        "plain_note": "one call per configuration: 2n level launches with one of the 64 lanes of "
+                                      "each wavefront busy"})
+            if name == "plain_single":
+                Gh = G.cpu().numpy().reshape(nmat, n0, n0)
+                t0 = time.perf_counter()
+                for _ in range(50):
+                    B.connected_sum_host(Gh[0] if w.variant == 0 else Gh, w.nflav, w.variant)
+                leg["host_call_configs_per_s"] = 50 / (time.perf_counter() - t0)
+        leg["vs_oracle_refs"] = _refs_stats(name, S_host)
+        if cpu_threads:
+            if name == "uneven":
+                # one configuration of each order, concurrently; extrapolated to the batch's order mix
+                per = {}
+                for k in range(6, 13):
+                    c = int(np.nonzero(d.n == k)[0][0])
+                    per[k] = c
+                from concurrent.futures import ThreadPoolExecutor
+                sig = d.delta[:nmat] / w.U
+
+                def order_time(k):
+                    t0 = time.perf_counter()
+                    _cpu_forward_rate(d, [per[k]], 1, w.variant, w.nflav, lambda c: sig)
+                    return k, time.perf_counter() - t0
+
+                t0 = time.perf_counter()
+                with ThreadPoolExecutor(max_workers=7) as ex:
+                    tk = dict(ex.map(order_time, range(6, 13)))
+                wall = time.perf_counter() - t0
+                core_s = sum(tk[k] * int((d.n == k).sum()) for k in tk)
+                leg["cpu_oracle"] = {"configs_per_s": nconf / (core_s / cpu_threads), "cores": cpu_threads,
+                                     "kind": "oracle, extrapolated",
+                                     "sample": "one configuration of each order 6..12 timed (%.0f s wall), "
+                                               "per-order single-core times x the batch's order counts / %d cores"
+                                               % (wall, cpu_threads),
+                                     "single_core_s_per_order": {int(k): v for k, v in tk.items()}}
+            else:
+                k = {"plain_single": 1, "plain_batch": 256, "sym_broken": 48}[name]
+                rate, dt = _cpu_forward_rate(d, list(range(k)), cpu_threads, w.variant, w.nflav, lambda c: None)
+                leg["cpu_oracle"] = {"configs_per_s": rate, "cores": cpu_threads, "kind": "oracle",
+                                     "sample": "first %d configurations, float64 DP forward, %.1f s wall" % (k, dt)}
+        b.close()
+        out[name] = leg
+        del G, S
+    return out
+
+
 def cpu_baseline(d, nsample, threads):
     """The oracle (C, float64) on host cores: propagators (numpy), reverse sweep
     with the forward sum (oracle DP), chain rule; one configuration per task."""
@@ -310,6 +524,8 @@ def main():
     ap.add_argument("--no-honeycomb", action="store_true", help="skip the sublattice (honeycomb) measurement")
     ap.add_argument("--no-mc", action="store_true", help="skip the Monte Carlo series measurement")
     ap.add_argument("--no-mask-only", action="store_true", help="skip the SU(2) mask-only comparison")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the other workloads (plain single, plain batch, symmetry broken, uneven)")
     ap.add_argument("--cpu-sample", type=int, default=1536)
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
@@ -527,14 +743,20 @@ def main():
     mcs = None if args.no_mc else mc_series(torch)
     mo = None if args.no_mask_only else mask_only_su2(B, torch, max(3, args.steps // 2))
 
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    # the host share of one GPU on the measurement boxes is 16 cores
+    threads = max(1, min(16, nproc))
+    S_host = S.cpu().numpy()
+    legs = None if args.no_workloads else workload_legs(B, torch, max(3, args.steps // 2),
+                                                        0 if args.no_cpu else threads)
     cpu = None
     if not args.no_cpu:
-        threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()))
         rate, dt = cpu_baseline(d, args.cpu_sample, threads)
         rate1, dt1 = cpu_baseline(d, 16, 1)
         cpu = {"value": rate, "unit": "configs/s", "cores": threads, "kind": "oracle",
                "sample": "%d configs of the same workload (propagators, float64 DP forward + reverse sweep, "
                          "chain rule), one config per thread, %.1f s wall" % (args.cpu_sample, dt),
+               "host_cpus_visible": nproc,
                "single_core_value": rate1,
                "single_core_sample": "16 configs on one thread, %.1f s" % dt1}
 
@@ -564,6 +786,7 @@ def main():
         "forward_kernel_ms": fwd_kernel_ms,
         "forward_plain_configs_per_s": nconf / (plain_ms * 1e-3),
         "forward_plain_synced_configs_per_s": plain_sync_rate,
+        "plain_note": "one call per configuration: 2n level launches with one of the 64 lanes of each wavefront busy",
         "batched_over_plain": (nconf / (fwd_ms * 1e-3)) / (nconf / (plain_ms * 1e-3)),
         "plain_equals_batched_bitwise": plain_equal,
         "adjoint_batched_configs_per_s": nconf / (acc["adj"] / args.steps * 1e-3),
@@ -571,7 +794,11 @@ def main():
         "adjoint_batched_over_plain": (nconf / (acc["adj"] / args.steps * 1e-3)) / adj_plain_rate,
         "adjoint_plain_check": {"configs": nadj, "S_equals_batched_bitwise": adj_plain_S_equal,
                                 "max_grad_dev_rel_to_max": adj_plain_grad_dev},
+        "vs_oracle_refs": _refs_stats(WORKLOAD, S_host) if nconf == 2048 else None,
         "roofline": {"bound": "alu", "kernel": REV_KERNEL % n,
+                     "note": "bound = the method's: FP64 ALU on algorithmic FLOP; the kernel itself streams every "
+                             "DP state through HBM (see hbm: AI ~1 FLOP/B, below the 9.8 FLOP/B ridge), which caps "
+                             "frac near AI x 8 TB/s / 78.6 TFLOP/s",
                      "unit_of_work": "one launch = one level of the reverse sweep over all %d configs "
                                      "(%d launches per sweep; per-launch figures are sweep averages)" % (nconf, nlaunch),
                      "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12, "unit": "TFLOP/s",
@@ -579,6 +806,7 @@ def main():
                      "flop_per_launch": flop_launch, "avg_launch_ms": launch_ms,
                      "flop_per_config_sweep": flop_rev, "hbm": hbm,
                      "forward_kernel_tflops": flop_fwd * nconf / (phases["forward"] / args.steps * 1e-3) / 1e12},
+        "workloads": legs,
         "sublattice_honeycomb_forward": hc,
         "mc_series": mcs,
         "su2_mask_only_vs_vertex": mo,

@@ -351,8 +351,11 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     const int wpb = blockDim.x >> 6;
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
-    const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
-    const int mb1 = min(mb0 + A.mpb, L.w);    // may be empty: the wave still joins the barriers
+    // the workgroup's block of masks; its wavefronts claim masks one at a time
+    // from an LDS counter, so that a wavefront that drew short rows takes more
+    const int blk0 = blockIdx.x * wpb * A.mpb;
+    const int blk1 = min(blk0 + wpb * A.mpb, L.w);   // may hold fewer masks than waves: they still join the barriers
+    __shared__ int next_mask;
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
     // wave-uniform bases; the lane's word is added at each access; flavour planes
@@ -373,10 +376,13 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             Gs_all[i] = gsrc[i];
             Gb_all[i] = 0.0;
         }
+        if (threadIdx.x == 0) next_mask = blk0 + wpb;   // masks blk0 .. blk0 + wpb - 1 go to the waves in order
         __syncthreads();
         const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
         double sacc = 0.0;
-        for (int mi = mb0; mi < mb1; ++mi) {
+        bool any = false;
+        for (int mi = blk0 + wave; mi < blk1;) {
+            any = true;
             const MaskRec<N> M = load_rec<N>(P, L.z + mi);
             const uint32_t ones = M.ones, twos = M.twos;
             double tb = 0.0;
@@ -401,8 +407,11 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
                 hs &= hs - 1u;
                 ++slot;
             }
+            int nx = 0;
+            if (lane == 0) nx = atomicAdd(&next_mask, 1);
+            mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
-        if (A.stubs && mb0 < mb1) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
+        if (A.stubs && any) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
         __syncthreads();
         double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * N * N * 64;
         for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
