@@ -92,7 +92,16 @@ enum { COS_UNIFORM = 0, COS_FLAVOUR = 1 };
  * 2^-n times the COS_FLAVOUR two-flavour sum of the same matrices.  With
  * COS_F_SUBLATTICE it is Alg. 1 with its sublattice labels.  Forward sums
  * and the reverse sweep. */
-enum { COS_F_STUBS = 1, COS_F_SUBLATTICE = 2, COS_F_MASK_ONLY = 4 };
+/* COS_F_DETERMINISTIC: gradients that are the same bit for bit on every run,
+ * whatever the launch shapes, the chunking of the groups or the reverse
+ * variant: the reverse sweep cuts each level's masks into a fixed number of
+ * parts, sums the dS/dG and dS/dsigma terms of a part in a fixed order in
+ * registers (one wavefront per matrix row) and the parts in a fixed order
+ * afterwards, with no atomics.  Slower than the default reverse (the child
+ * adjoints are read once per row of G, from the caches); the forward and S
+ * are unchanged (they are deterministic anyway).  Not combinable with
+ * COS_F_SUBLATTICE. */
+enum { COS_F_STUBS = 1, COS_F_SUBLATTICE = 2, COS_F_MASK_ONLY = 4, COS_F_DETERMINISTIC = 8 };
 
 typedef struct cos_batch_s *cos_batch_t;
 
@@ -112,9 +121,12 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
  * first reverse call).  A batch whose groups of 64 configurations do not all
  * fit runs them in chunks of as many groups as fit (at least one), one after
  * the other; results do not depend on the chunking (S bitwise).  0 (the
- * initial setting) selects a third of the device's memory (96 GB on
- * MI355X).  COS_EINVAL for bytes < 0.  Batches already planned keep their
- * bound. */
+ * initial setting) bounds the windows by 45% of the device memory free at
+ * cos_batch_create and the stored levels by 90% of the memory free at the
+ * first reverse call.  Whatever the bound, an allocation that fails is
+ * retried with every chunk halved, down to one group per chunk (then
+ * COS_ENOMEM).  COS_EINVAL for bytes < 0.  Batches already planned keep
+ * their bound. */
 cos_status cos_set_workspace_limit(int64_t bytes);
 cos_status cos_batch_destroy(cos_batch_t b);
 
@@ -232,13 +244,37 @@ cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat,
 cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
                            int64_t *shift_edges, int64_t *masks, int64_t *rows);
 
+/* Memory of the reverse sweep.  The reverse levels need the forward states of
+ * every level; segments = 1 stores them all (about 7 times the largest
+ * level per group at n = 12), segments = 2 stores only levels h+1..2n during
+ * the forward, reverses them, then computes levels 1..h again into the same
+ * store and reverses those (h chosen so that both halves hold about the same
+ * number of rows: about 40% less memory per group, the lower levels'
+ * forward run twice).  0 (the default) takes 2 when storing every level would
+ * split the batch's groups into several chunks (cos_set_workspace_limit),
+ * else 1.  Results are the same either way (S bitwise; gradients up to the
+ * summation order of their accumulation).  If the reverse workspace already
+ * exists it is freed (after waiting for the device) and planned again at the
+ * next reverse call.  COS_EINVAL for other values. */
+cos_status cos_batch_set_adjoint_segments(cos_batch_t b, int32_t segments);
+/* The reverse-sweep plan of order n, after a reverse call: the split level
+ * (0: every level stored), groups of 64 configurations per chunk, and bytes
+ * of workspace per group (stored forward states and the two adjoint
+ * windows).  Any output may be NULL.  COS_EINVAL before the first reverse
+ * call or for an order the batch does not have. */
+cos_status cos_batch_adjoint_plan(cos_batch_t b, int32_t n, int32_t *split_level, int32_t *groups_per_chunk,
+                                  int64_t *bytes_per_group);
+
 /* Autotuner (Results, GPU parallelization: launch shape per problem size).
  * For every order in the batch, times the level kernels over the caller's
  * inputs for each candidate launch shape -- wavefronts per workgroup of the
  * forward kernel (4, 8; 8, 16 with COS_F_SUBLATTICE) and the most masks
  * (state-table tiles) per wavefront of the forward (1, 2, 4, 8, 16) and, when
- * d_out_bar is not NULL, of the reverse kernel (1, 2, 4, 6, 7, 8, 10, 12, 16)
- * -- keeps the fastest per order and uses it for every later call on b.  Arguments as cos_connected_sum_batched / _adjoint; the output
+ * d_out_bar is not NULL, of the reverse kernel (2, 4, 6, 8, 12, 16, 24, 32;
+ * a reverse level is cut into as few rounds of one workgroup per CU as that
+ * cap allows, its masks spread evenly) -- keeps the fastest per order and
+ * uses it for every later call on b.  Arguments as cos_connected_sum_batched
+ * / _adjoint; the output
  * buffers are overwritten and on return hold what a call with the chosen
  * shapes writes.  Synchronous (waits for the stream).  S does not depend on
  * the launch shape (bitwise); the gradients do only through the summation
@@ -251,11 +287,22 @@ cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves,
                                   int32_t *fwd_masks, int32_t *adj_masks);
 /* Set the launch shape of order n instead of tuning it (for instance one that
  * cos_batch_autotune found before): fwd_waves in [1, 8] ([1, 16] with
- * COS_F_SUBLATTICE), fwd_masks and adj_masks in [1, 16] (the forward clamps
+ * COS_F_SUBLATTICE), fwd_masks in [1, 16], adj_masks in [1, 64] (the forward clamps
  * its masks per wavefront to 4 with several flavour slots).  COS_EINVAL for
  * values outside these ranges or an order the batch does not have. */
 cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_waves, int32_t fwd_masks,
                                       int32_t adj_masks);
+
+/* The reverse level kernel of order n accumulates dS/dG either in LDS (one
+ * accumulator per workgroup of adj_waves 16 wavefronts, added to the packed
+ * gradient once per workgroup; global_atomics = 0) or with global FP64
+ * atomics straight into the packed gradient (LDS holds only G, so
+ * workgroups are smaller and more fit a CU; global_atomics = 1, waves in
+ * [1, 16]).  cos_batch_autotune tries both; these read and set the choice
+ * (labelled batches keep the LDS accumulator).  COS_EINVAL for other values
+ * or an order the batch does not have. */
+cos_status cos_batch_reverse_variant(cos_batch_t b, int32_t n, int32_t *global_atomics, int32_t *waves);
+cos_status cos_batch_set_reverse_variant(cos_batch_t b, int32_t n, int32_t global_atomics, int32_t waves);
 
 /* Phase timing, a measurement aid.  After cos_batch_timing_enable(b, 1),
  * every forward or adjoint call on b records HIP events on its own stream at
@@ -326,6 +373,16 @@ cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *val
 cos_status cos_cdet_workspace(int32_t n, int32_t nconf, int32_t precision, uint64_t *bytes);
 cos_status cos_cdet_su2(int32_t nconf, int32_t n, const double *d_A, int32_t precision, double eps,
                         void *d_work, uint64_t work_bytes, double *d_out, void *stream);
+
+/* Testing aid for the error paths (no effect unless called): of the device
+ * allocations (kind 0) or kernel launches (kind 1) the library makes from
+ * now on, the next `skip` proceed and the `count` after them fail -- an
+ * allocation as if the device were out of memory (the calls then return
+ * COS_ENOMEM, or retry the level workspaces with smaller chunks, see
+ * cos_set_workspace_limit), a launch is skipped and its call returns
+ * COS_EDEVICE (launches queued before it stay queued).  count = 0 clears.
+ * Process-wide; COS_EINVAL for another kind or negative numbers. */
+cos_status cos_inject_failures(int32_t kind, int32_t skip, int32_t count);
 
 /* Diagnostics. */
 const char *cos_status_string(cos_status s);

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcos.so")
 
 UNIFORM, FLAVOUR = 0, 1
-F_STUBS, F_SUBLATTICE, F_MASK_ONLY = 1, 2, 4
+F_STUBS, F_SUBLATTICE, F_MASK_ONLY, F_DETERMINISTIC = 1, 2, 4, 8
 NMAX, FMAX, NMAX_SUBLATTICE = 12, 16, 8
 
 EXPORTED = (
@@ -26,7 +26,8 @@ EXPORTED = (
     "cos_batch_timing_enable", "cos_batch_timing_read", "cos_batch_autotune", "cos_batch_launch_shape",
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
     "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape", "cos_set_workspace_limit",
-    "cos_connected_sum_static",
+    "cos_connected_sum_static", "cos_inject_failures", "cos_batch_set_adjoint_segments",
+    "cos_batch_adjoint_plan", "cos_batch_reverse_variant", "cos_batch_set_reverse_variant",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -68,6 +69,11 @@ def _load():
         "cos_batch_autotune": ([p, p, p, p, d, p, p, p, p, p], i32),
         "cos_batch_set_launch_shape": ([p, i32, i32, i32, i32], i32),
         "cos_connected_sum_static": ([i32, i32, i32, i32, i32, p, p, d, p, p], i32),
+        "cos_inject_failures": ([i32, i32, i32], i32),
+        "cos_batch_set_adjoint_segments": ([p, i32], i32),
+        "cos_batch_reverse_variant": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
+        "cos_batch_set_reverse_variant": ([p, i32, i32, i32], i32),
+        "cos_batch_adjoint_plan": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), P64], i32),
         "cos_batch_launch_shape": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
     }
     for name, (args, res) in sig.items():
@@ -143,9 +149,15 @@ def _geometry_buffers(nconf, n, voff, sites, tau, Goff, G, dG):
 
 
 def set_workspace_limit(nbytes: int):
-    """Bound each level workspace of batches planned from now on (0: a third
-    of the device memory)."""
+    """Bound each level workspace of batches planned from now on (0: a share
+    of the device memory free when the workspace is made)."""
     _check(lib.cos_set_workspace_limit(int(nbytes)), "cos_set_workspace_limit")
+
+
+def inject_failures(kind: int, skip: int, count: int):
+    """Make the library's next device allocations (kind 0) or kernel launches
+    (kind 1) fail after `skip` successes, `count` times (testing aid)."""
+    _check(lib.cos_inject_failures(int(kind), int(skip), int(count)), "cos_inject_failures")
 
 
 def plan_counts(n: int) -> dict:
@@ -206,7 +218,7 @@ class Batch:
     """Plan for a batch of configurations with orders ``n`` (host sequence)."""
 
     def __init__(self, n, nflav: int, variant: int = UNIFORM, stubs: bool = False, sublattice: bool = False,
-                 mask_only: bool = False):
+                 mask_only: bool = False, deterministic: bool = False):
         n = np.ascontiguousarray(np.asarray(n, dtype=np.int32).reshape(-1))
         self.n = n
         self.nconf = int(n.size)
@@ -215,11 +227,12 @@ class Batch:
         self.stubs = bool(stubs)
         self.sublattice = bool(sublattice)
         self.mask_only = bool(mask_only)
+        self.deterministic = bool(deterministic)
         self.nmat = self.nflav if self.variant == FLAVOUR else 1
         self.nstub = self.nmat
         h = ctypes.c_void_p()
         flags = ((F_STUBS if self.stubs else 0) | (F_SUBLATTICE if self.sublattice else 0)
-                 | (F_MASK_ONLY if self.mask_only else 0))
+                 | (F_MASK_ONLY if self.mask_only else 0) | (F_DETERMINISTIC if self.deterministic else 0))
         _check(lib.cos_batch_create(self.nconf, _ptr(n), self.nflav, self.variant, flags, ctypes.byref(h)),
                "cos_batch_create")
         self._h = h
@@ -288,6 +301,30 @@ class Batch:
     def set_launch_shape(self, n: int, fwd_waves: int, fwd_masks: int, adj_masks: int):
         _check(lib.cos_batch_set_launch_shape(self._h, int(n), int(fwd_waves), int(fwd_masks), int(adj_masks)),
                "cos_batch_set_launch_shape")
+
+    def reverse_variant(self, n: int):
+        """{'global_atomics': 0 or 1, 'waves': wavefronts per workgroup} of the reverse kernel of order n."""
+        g, w = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.cos_batch_reverse_variant(self._h, int(n), ctypes.byref(g), ctypes.byref(w)),
+               "cos_batch_reverse_variant")
+        return {"global_atomics": g.value, "waves": w.value}
+
+    def set_reverse_variant(self, n: int, global_atomics: int, waves: int):
+        _check(lib.cos_batch_set_reverse_variant(self._h, int(n), int(global_atomics), int(waves)),
+               "cos_batch_set_reverse_variant")
+
+    def set_adjoint_segments(self, segments: int):
+        """0 automatic, 1 store every forward level, 2 two segments (lower
+        levels recomputed; less memory)."""
+        _check(lib.cos_batch_set_adjoint_segments(self._h, int(segments)), "cos_batch_set_adjoint_segments")
+
+    def adjoint_plan(self, n: int):
+        """Reverse-sweep plan of order n after a reverse call: split level,
+        groups per chunk, workspace bytes per group."""
+        h, c, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.cos_batch_adjoint_plan(self._h, int(n), ctypes.byref(h), ctypes.byref(c), ctypes.byref(nb)),
+               "cos_batch_adjoint_plan")
+        return {"split_level": h.value, "groups_per_chunk": c.value, "bytes_per_group": nb.value}
 
     def timing(self, enable: bool = True):
         """Record HIP events at the phase boundaries of every later call."""

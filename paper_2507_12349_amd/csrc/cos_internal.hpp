@@ -131,6 +131,8 @@ struct LvlArgs {
     int32_t F_row0;
     int32_t level, group0, nfs, stubs, mpb;
     int32_t mask_only;        // SU(2) mask-only rules (two spin blocks as the two planes)
+    int32_t gacc;             // reverse: dS/dG terms by global atomics instead of an LDS accumulator
+    int32_t det_groups;       // deterministic reverse: groups of the order (stride of the partial sums)
     double W;                 // factor of one closed cycle: w * nflav (uniform) or w
     double *out;              // forward, last level: S per configuration (may be null)
     const double *out_bar;    // reverse: dL/dS per configuration
@@ -148,9 +150,18 @@ hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb,
 // sublattice reverse level: adj_waves_per_block() wavefronts per workgroup
 hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipStream_t s);
 // nblocks = blocks of `a.mpb` masks; `wpb` wavefronts per workgroup (forward:
-// at most 8; the reverse kernel always runs adj_waves_per_block())
+// at most 8; reverse: at most 16, adj_waves_per_block() with the LDS accumulator)
 hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s);
 int adj_waves_per_block();
+// deterministic reverse sweep: every level's masks in kDetParts fixed parts;
+// Gbar_T / sbar_T of the LvlArgs point to the partial sums
+// [part][group][flavour][v][w][64] and [part][group][flavour][v][64]
+constexpr int kDetParts = 32;
+hipError_t launch_level_det(const LvlArgs &a, int ngroups, hipStream_t s);
+// GbT = sum of the gsize-element parts in order; sbT (ssize elements,
+// [group][flavour][64]) = sum over parts and slots v < n
+hipError_t launch_det_reduce(const double *Gpart, const double *Spart, int64_t gsize, int64_t ssize, int n,
+                             double *GbT, double *sbT, hipStream_t s);
 // most masks per wavefront of the forward kernel when there are several flavours
 constexpr int kMultiMasks = 4;
 // launchers (cos_kernels.hip)

@@ -281,8 +281,8 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
 // workgroup and flavour; only the (v, w) pairs a row can touch (v current,
 // w open or the head) are accumulated.
 // ---------------------------------------------------------------------------
-template <int N, bool MASK>
-__device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
+template <int N, bool MASK, bool GACC>
+__device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr, double *gbg,
                                         const double *__restrict__ F, const double *__restrict__ Bn,
                                         double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
                                         int64_t npl, int lam, int u, int r, bool start, double tb, double sgx,
@@ -336,17 +336,23 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
         lane_st_nt(dst + v * 64, lane8, b);
 #pragma unroll
         for (int w = 0; w < N; ++w)
-            if (need & (1u << w))   // wave-uniform
-                __hip_atomic_fetch_add(Gb + (v * N + w) * 64, f[v] * a[w], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (need & (1u << w)) {   // wave-uniform
+                if (GACC)
+                    lane_atomic_add(gbg + (v * N + w) * 64, lane8, f[v] * a[w]);
+                else
+                    __hip_atomic_fetch_add(Gb + (v * N + w) * 64, f[v] * a[w], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
     }
 }
 
-template <int N, bool MASK>
+// GACC: the dS/dG terms go straight to the packed gradient with global
+// atomics (LDS holds only G), instead of a workgroup accumulator in LDS
+template <int N, bool MASK, bool GACC>
 __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
     double *Gs_all = lds;                     // [N * N][64]  G of the flavour
-    double *Gb_all = lds + N * N * 64;        // [N * N][64]  dS/dG of the flavour, this workgroup
+    double *Gb_all = lds + N * N * 64;        // [N * N][64]  dS/dG of the flavour, this workgroup (not GACC)
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
     const DevPlan &P = A.plan;
@@ -374,8 +380,9 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
         const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * N * N * 64;
         for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
             Gs_all[i] = gsrc[i];
-            Gb_all[i] = 0.0;
+            if (!GACC) Gb_all[i] = 0.0;
         }
+        double *gbg = A.Gbar_T + (int64_t)(g * nfs + lam) * N * N * 64;   // wave-uniform base
         if (threadIdx.x == 0) next_mask = blk0 + wpb;   // masks blk0 .. blk0 + wpb - 1 go to the waves in order
         __syncthreads();
         const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
@@ -400,8 +407,8 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             int u = 0, slot = 0;
             while (true) {
                 if (!(MASK && empty_plane(u, lam, twos)))
-                    adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start, tb,
-                                     sg * sc, sc, sacc);
+                    adj_row<N, MASK, GACC>(M, gaddr, gbaddr, gbg, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot,
+                                           start, tb, sg * sc, sc, sacc);
                 if (!hs) break;
                 u = __builtin_ctz(hs);
                 hs &= hs - 1u;
@@ -412,12 +419,138 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
         if (A.stubs && any) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
+        if (GACC) continue;
         __syncthreads();
         double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * N * N * 64;
         for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
             const double x = Gb_all[i];
             if (x != 0.0) atomicAdd(gb + i, x);
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reverse, deterministic: the same rules as level_adj_kernel, with an order of
+// summation that depends on nothing but the order n.  A level's masks are cut
+// into kDetParts fixed parts; a workgroup of N wavefronts takes one part of
+// one group, wavefront v owns slot v: it forms B(m, u)[v], keeps row v of G
+// and the partial sums dS/dG[v][*] (and its shift term) in registers over the
+// part's rows in order, and adds them to the part's own slot of a partial
+// buffer (no atomics: one wavefront per slot and level, the levels follow one
+// another on the stream).  det_reduce_kernel then sums the parts in order.
+// The child adjoints of a row are read by each of its current wavefronts;
+// those reads hit the caches after the first.
+// ---------------------------------------------------------------------------
+template <int N, bool MASK>
+__global__ void __launch_bounds__(64 * COS_NMAX) level_adj_det_kernel(const LvlArgs A) {
+    const int lane = threadIdx.x & 63, v = COS_RF(threadIdx.x >> 6);   // the wave's slot: uniform
+    const DevPlan &P = A.plan;
+    const int4 L = load_level(P, A.level);
+    const int part = blockIdx.x;
+    const int lo = (int)(((int64_t)part * L.w) / kDetParts), hi = (int)(((int64_t)(part + 1) * L.w) / kDetParts);
+    const int gl = blockIdx.y, g = A.group0 + gl;
+    const int nfs = A.nfs;
+    const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * N * 64;
+    const int64_t fpl = A.F_frows * N * 64, cpl = A.cur_frows * N * 64, npl = A.nxt_frows * N * 64;
+    const double *__restrict__ Bn = A.cur + gl * A.cur_gstride;   // level + 1
+    double *__restrict__ Bc = A.nxt + gl * A.nxt_gstride;         // level
+    const uint32_t lane8 = (uint32_t)lane * 8u, vbit = 1u << v;
+    const int cfg = A.lane_cfg[g * 64 + lane];
+    const double obar = cfg >= 0 ? A.out_bar[cfg] : 0.0;
+    const bool top = A.level == 2 * N, start = A.level == 1;
+    if (lo >= hi) return;
+
+    for (int lam = 0; lam < nfs; ++lam) {
+        const double *__restrict__ grow = A.GT + ((int64_t)(g * nfs + lam) * N + v) * N * 64;
+        double gv[N], gb[N];
+#pragma unroll
+        for (int w = 0; w < N; ++w) {
+            gv[w] = lane_ld(grow + w * 64, lane8);
+            gb[w] = 0.0;
+        }
+        const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
+        double sacc = 0.0;
+        for (int mi = lo; mi < hi; ++mi) {
+            const MaskRec<N> M = load_rec<N>(P, L.z + mi);
+            const uint32_t ones = M.ones, twos = M.twos;
+            double tb = 0.0;
+            if (top) {
+                tb = obar;
+            } else if (ones) {
+                const int h = __builtin_ctz(ones);
+                const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
+                for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
+                    tb += lane_ld(Bn + k * cpl + (int64_t)crow * N * 64 + h * 64, lane8);
+            }
+            tb *= A.W;
+            const double sc = (M.code == 1 ? 2.0 : 1.0);
+            uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
+            int u = 0, slot = 0;
+            while (true) {
+                const uint32_t cm = current_set(u, ones, twos);
+                if ((cm & vbit) && !(MASK && empty_plane(u, lam, twos))) {
+                    const int r = M.rb + slot;
+                    const double fv = start ? (v == 0 ? 1.0 : 0.0)
+                                            : lane_ld_nt(F + lam * fpl + (int64_t)r * N * 64 + v * 64, lane8);
+                    double a[N];
+                    double bcv = 0.0;
+#pragma unroll
+                    for (int w = 0; w < N; ++w) {
+                        const uint32_t bit = 1u << w;
+                        const bool open = !(twos & bit), first = !(ones & bit);
+                        const int crow = open ? M.crb[w] + head_slot(u, first ? twos : (twos | bit)) : 0;
+                        const double bc = lane_ld(Bn + (open ? lam * cpl + (int64_t)crow * N * 64 + w * 64 : 0), lane8);
+                        a[w] = open ? (first ? (MASK ? bc : 2.0 * bc) : bc) : 0.0;
+                        if (MASK && w == 0 && u == 0) a[w] = 0.0;   // no extension onto the head point
+                        if (w == v) bcv = bc;
+                    }
+                    // the shift edge out of slot v (child adjoint without the close term)
+                    const bool vopen = !(twos & vbit), vfirst = !(ones & vbit);
+                    if (vopen && !vfirst) sacc = __builtin_fma(-sc * fv, bcv, sacc);
+#pragma unroll
+                    for (int w = 0; w < N; ++w) a[w] = (w == u) ? a[w] + tb : a[w];
+                    const uint32_t need = (~twos | (1u << u)) & ((1u << N) - 1u);
+                    double b = 0.0;
+#pragma unroll
+                    for (int w = 0; w < N; ++w) b = __builtin_fma(gv[w], a[w], b);
+                    if (ones & vbit) b = __builtin_fma(-sg * sc, (v == u) ? a[v] - tb : a[v], b);
+                    lane_st_nt(Bc + lam * npl + (int64_t)r * N * 64 + v * 64, lane8, b);
+#pragma unroll
+                    for (int w = 0; w < N; ++w)
+                        if (need & (1u << w)) gb[w] = __builtin_fma(fv, a[w], gb[w]);   // wave-uniform test
+                }
+                if (!hs) break;
+                u = __builtin_ctz(hs);
+                hs &= hs - 1u;
+                ++slot;
+            }
+        }
+        // this part's slot of the partial sums (one wavefront per slot and level)
+        double *gp = A.Gbar_T + (((int64_t)part * A.det_groups + g) * nfs + lam) * N * N * 64 + (int64_t)v * N * 64;
+#pragma unroll
+        for (int w = 0; w < N; ++w) lane_st(gp + w * 64, lane8, lane_ld(gp + w * 64, lane8) + gb[w]);
+        if (A.stubs) {
+            double *sp = A.sbar_T + ((((int64_t)part * A.det_groups + g) * nfs + lam) * N + v) * 64;
+            lane_st(sp, lane8, lane_ld(sp, lane8) + sacc);
+        }
+    }
+}
+
+// sums the parts in order: GbT[i] = sum_p Gpart[p][i], sbT[g][l] = sum_p sum_v Spart[p][g][l][v]
+__global__ void det_reduce_kernel(const double *__restrict__ Gpart, const double *__restrict__ Spart, int64_t gsize,
+                                  int64_t ssize, int n, double *__restrict__ GbT, double *__restrict__ sbT) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < gsize) {
+        double x = 0.0;
+        for (int p = 0; p < kDetParts; ++p) x += Gpart[(int64_t)p * gsize + i];
+        GbT[i] = x;
+    }
+    if (Spart && i < ssize) {   // i = (g * nfs + l) * 64 + lane
+        const int64_t gl = i >> 6, lane = i & 63;
+        double x = 0.0;
+        for (int p = 0; p < kDetParts; ++p)
+            for (int v = 0; v < n; ++v) x += Spart[(((int64_t)p * (ssize >> 6) + gl) * n + v) * 64 + lane];
+        sbT[i] = x;
     }
 }
 
@@ -477,7 +610,34 @@ hipError_t launch_iota(int32_t *p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-// the reverse sweep shares one LDS accumulator among the wavefronts of a
+hipError_t launch_level_det(const LvlArgs &a, int ngroups, hipStream_t s) {
+    const int n = a.plan.n;
+    const dim3 grid((unsigned)kDetParts, (unsigned)ngroups);
+    switch (n) {
+#define COS_DET_CASE(K)                                                                              \
+    case K:                                                                                          \
+        if (a.mask_only) hipLaunchKernelGGL((level_adj_det_kernel<K, true>), grid, dim3(64 * K), 0, s, a); \
+        else hipLaunchKernelGGL((level_adj_det_kernel<K, false>), grid, dim3(64 * K), 0, s, a);         \
+        break;
+        COS_DET_CASE(1) COS_DET_CASE(2) COS_DET_CASE(3) COS_DET_CASE(4)
+        COS_DET_CASE(5) COS_DET_CASE(6) COS_DET_CASE(7) COS_DET_CASE(8)
+        COS_DET_CASE(9) COS_DET_CASE(10) COS_DET_CASE(11) COS_DET_CASE(12)
+#undef COS_DET_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_det_reduce(const double *Gpart, const double *Spart, int64_t gsize, int64_t ssize, int n,
+                             double *GbT, double *sbT, hipStream_t s) {
+    const int64_t tot = (Spart && ssize > gsize) ? ssize : gsize;
+    if (tot <= 0) return hipSuccess;
+    hipLaunchKernelGGL(det_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, Gpart, Spart, gsize,
+                       ssize, n, GbT, sbT);
+    return hipGetLastError();
+}
+
+// the reverse sweep shares one LDS accumulator// the reverse sweep shares one LDS accumulator among the wavefronts of a
 // workgroup: large workgroups
 int adj_waves_per_block() { return 16; }
 
@@ -491,24 +651,32 @@ hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups
     const int n = a.plan.n;
     if (!reverse && (wpb < 1 || wpb > 8)) return hipErrorInvalidValue;
     if (reverse) {
-        const int wpa = adj_waves_per_block();
-        const size_t shm = 2 * (size_t)n * n * 64 * sizeof(double);
+        // the reverse takes `wpb` as its workgroup size (adj_waves_per_block() for the LDS accumulator)
+        const int wpa = wpb;
+        if (wpa < 1 || wpa > 16) return hipErrorInvalidValue;
+        const size_t shm = (a.gacc ? 1 : 2) * (size_t)n * n * 64 * sizeof(double);
         const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups);
         switch (n) {
+#define COS_ADJ_LAUNCH(K, M, GA)                                                                  \
+    {                                                                                             \
+        hipError_t e = allow_lds((const void *)level_adj_kernel<K, M, GA>, shm);                  \
+        if (e != hipSuccess) return e;                                                            \
+        hipLaunchKernelGGL((level_adj_kernel<K, M, GA>), grid, dim3(64 * wpa), shm, s, a);        \
+    }
 #define COS_ADJ_CASE(K)                                                                           \
     case K: {                                                                                     \
-        const void *fn = a.mask_only ? (const void *)level_adj_kernel<K, true>                    \
-                                     : (const void *)level_adj_kernel<K, false>;                  \
-        hipError_t e = allow_lds(fn, shm);                                                        \
-        if (e != hipSuccess) return e;                                                            \
-        if (a.mask_only) hipLaunchKernelGGL((level_adj_kernel<K, true>), grid, dim3(64 * wpa), shm, s, a);  \
-        else hipLaunchKernelGGL((level_adj_kernel<K, false>), grid, dim3(64 * wpa), shm, s, a);             \
+        if (a.mask_only) {                                                                        \
+            if (a.gacc) COS_ADJ_LAUNCH(K, true, true) else COS_ADJ_LAUNCH(K, true, false)         \
+        } else {                                                                                  \
+            if (a.gacc) COS_ADJ_LAUNCH(K, false, true) else COS_ADJ_LAUNCH(K, false, false)       \
+        }                                                                                         \
         break;                                                                                    \
     }
             COS_ADJ_CASE(1) COS_ADJ_CASE(2) COS_ADJ_CASE(3) COS_ADJ_CASE(4)
             COS_ADJ_CASE(5) COS_ADJ_CASE(6) COS_ADJ_CASE(7) COS_ADJ_CASE(8)
             COS_ADJ_CASE(9) COS_ADJ_CASE(10) COS_ADJ_CASE(11) COS_ADJ_CASE(12)
 #undef COS_ADJ_CASE
+#undef COS_ADJ_LAUNCH
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -316,8 +316,10 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
     const int i0 = SubAdjShape<N>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
-    const int mb0 = (blockIdx.x * wpb + wave) * A.mpb;
-    const int mb1 = min(mb0 + A.mpb, L.w);    // may be empty: the wave still joins the barriers
+    // the workgroup's block of masks, claimed one at a time by its wavefronts
+    const int blk0 = blockIdx.x * wpb * A.mpb;
+    const int blk1 = min(blk0 + wpb * A.mpb, L.w);   // may hold fewer masks than waves: they still join the barriers
+    __shared__ int next_mask;
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
     const double *__restrict__ F = A.F + gl * A.F_gstride + (int64_t)A.F_row0 * D * 64;
@@ -337,8 +339,9 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
             Gs_all[i] = gsrc[i];
             Gb_all[i] = 0.0;
         }
+        if (threadIdx.x == 0) next_mask = blk0 + wpb;   // masks blk0 .. blk0 + wpb - 1 go to the waves in order
         __syncthreads();
-        for (int mi = mb0; mi < mb1; ++mi) {
+        for (int mi = blk0 + wave; mi < blk1;) {
             const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
             const uint32_t ones = M.ones, twos = M.twos;
             double tb = 0.0;
@@ -370,6 +373,9 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
                 hs &= hs - 1u;
                 su = 0;
             }
+            int nx = 0;
+            if (lane == 0) nx = atomicAdd(&next_mask, 1);
+            mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
         __syncthreads();
         double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64 + (int64_t)i0 * D * 64;

@@ -43,6 +43,36 @@ cos_status fail(cos_status s, const char *fmt, ...) {
             return fail(COS_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));           \
     } while (0)
 
+// failures injected by cos_inject_failures: after `skip` successes, `count`
+// device allocations (kind 0) or kernel launches (kind 1) fail
+std::atomic<int> g_inj_skip[2], g_inj_count[2];
+
+bool injected(int kind) {
+    if (g_inj_count[kind].load() <= 0) return false;
+    if (g_inj_skip[kind].load() > 0) {
+        --g_inj_skip[kind];
+        return false;
+    }
+    --g_inj_count[kind];
+    return true;
+}
+
+// every device allocation of the library goes through here
+hipError_t dev_malloc(void **p, size_t bytes) {
+    if (injected(0)) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+// a kernel launch of the library; an injected failure skips the launch
+#define LAUNCH_TRY(expr)                                                                       \
+    do {                                                                                       \
+        if (injected(1)) return fail(COS_EDEVICE, "%s failed: injected launch failure", #expr); \
+        HIP_TRY(expr);                                                                         \
+    } while (0)
+
 // ---------------------------------------------------------------------------
 // Host plan: the state tables for one order n (identical for every
 // configuration and flavour).  Rows are ordered by level, then mask code,
@@ -249,10 +279,38 @@ std::shared_ptr<HostPlan> host_plan(int n, bool sub = false) {
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// upper bound on each of a batch's two level workspaces (bytes), fixed when
-// the batch is planned: cos_set_workspace_limit, or by default a third of the
-// device's memory.  A batch whose groups do not fit runs them in chunks.
+// upper bound on each of a batch's two level workspaces (bytes):
+// cos_set_workspace_limit, or by default a share of the device memory free
+// when the workspace is made.  A batch whose groups do not fit runs them in
+// chunks.
 std::atomic<int64_t> g_ws_limit{0};
+
+int64_t workspace_cap(int64_t lim, double share_of_free) {
+    if (lim > 0) return lim;
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) return 0;
+    return (int64_t)(share_of_free * (double)fr);
+}
+
+// allocates `doubles_of()` doubles after fitting the chunks under `cap`
+// bytes; while the allocation fails, halves every chunk of more than one
+// group and tries again
+template <class Chunk, class Size>
+cos_status alloc_chunked(double **out, std::vector<int> &chunks, const std::vector<int> &ngroups, int64_t cap,
+                         Chunk per_group_doubles, Size doubles_of, const char *what) {
+    for (size_t i = 0; i < chunks.size(); ++i)
+        chunks[i] = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups[i], cap / (8 * per_group_doubles(i))));
+    while (true) {
+        const int64_t n = doubles_of();
+        if (dev_malloc((void **)out, sizeof(double) * (size_t)std::max<int64_t>(n, 1)) == hipSuccess) return COS_OK;
+        (void)hipGetLastError();
+        *out = nullptr;
+        bool halved = false;
+        for (int &c : chunks)
+            if (c > 1) c = (c + 1) / 2, halved = true;
+        if (!halved) return fail(COS_ENOMEM, "%s allocation failed (%.1f MB, one group per chunk)", what, 8.0 * n / 1e6);
+    }
+}
 
 cos_status device_plan(int dev, int n, bool sub, DevPlan *out) {
     std::lock_guard<std::mutex> lk(g_mu);
@@ -265,7 +323,7 @@ cos_status device_plan(int dev, int n, bool sub, DevPlan *out) {
     auto hp = host_plan(n, sub);
     const size_t s1 = align_up(hp->mrec.size() * 4), s2 = align_up(hp->levels.size() * sizeof(int4));
     char *mem = nullptr;
-    if (hipMalloc((void **)&mem, s1 + s2) != hipSuccess)
+    if (dev_malloc((void **)&mem, s1 + s2) != hipSuccess)
         return fail(COS_ENOMEM, "device allocation of the state tables for n=%d failed", n);
     hipError_t e = hipMemcpy(mem, hp->mrec.data(), hp->mrec.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(mem + s1, hp->levels.data(), hp->levels.size() * sizeof(int4), hipMemcpyHostToDevice);
@@ -303,10 +361,12 @@ cos_status check_device(int *dev, int *ncu, int64_t *mem = nullptr) {
 cos_status check_common(int32_t nflav, int32_t variant, int32_t flags) {
     if (variant != COS_UNIFORM && variant != COS_FLAVOUR)
         return fail(COS_EINVAL, "variant must be COS_UNIFORM (0) or COS_FLAVOUR (1), got %d", variant);
-    const int32_t known = COS_F_STUBS | COS_F_SUBLATTICE | COS_F_MASK_ONLY;
+    const int32_t known = COS_F_STUBS | COS_F_SUBLATTICE | COS_F_MASK_ONLY | COS_F_DETERMINISTIC;
     if (flags & ~known) return fail(COS_EINVAL, "unknown flag bits 0x%x", flags & ~known);
     if ((flags & COS_F_STUBS) && (flags & COS_F_SUBLATTICE))
         return fail(COS_EINVAL, "COS_F_STUBS cannot be combined with COS_F_SUBLATTICE");
+    if ((flags & COS_F_DETERMINISTIC) && (flags & COS_F_SUBLATTICE))
+        return fail(COS_EINVAL, "COS_F_DETERMINISTIC cannot be combined with COS_F_SUBLATTICE");
     if (nflav < 1 || nflav > COS_FMAX) return fail(COS_ERANGE, "nflav must be in [1, %d], got %d", COS_FMAX, nflav);
     if (flags & COS_F_MASK_ONLY) {
         if (variant != COS_FLAVOUR || nflav != 2)
@@ -331,6 +391,8 @@ struct LaunchShape {
     int fwd_wpb = 8;    // forward: wavefronts per workgroup (<= 8; sublattice: <= 16, default 16)
     int fwd_cap = 0;    // forward: most masks per wavefront (0: by flavour count)
     int adj_cap = 8;    // reverse: most masks per wavefront
+    int adj_wpb = 16;   // reverse: wavefronts per workgroup
+    int adj_gacc = 0;   // reverse: dS/dG by global atomics (LDS holds only G) instead of an LDS accumulator
 };
 
 // all configurations of one order inside a batch
@@ -339,7 +401,10 @@ struct OrderGroup {
     int ngroups = 0;                   // 64 configurations per group (one per lane)
     int64_t gt_off = 0, sig_off = 0, lane_off = 0;   // offsets into the packed buffers
     int chunk_fwd = 1, chunk_adj = 1;  // groups per chunk (bounded workspace)
+    int adj_split = 0;                 // reverse sweep: 0 = every forward level stored; h > 0 = levels
+                                       // h+1..2n stored by the forward, levels 1..h recomputed later
     int64_t gb_off = 0, sb_off = 0;    // offsets into the packed gradient accumulators
+    int64_t sp_off = 0;                // deterministic reverse: offset into the shift partial sums
     LaunchShape shape;                 // launch shape of the level kernels (autotuned)
     bool sub = false;                  // sublattice-labelled states (2n slots per row)
     std::shared_ptr<HostPlan> hp;
@@ -348,7 +413,8 @@ struct OrderGroup {
 
 struct cos_batch_s {
     int dev = 0, ncu = 0;
-    int64_t ws_cap = 0;                // bytes per level workspace (chunking of the groups)
+    int64_t ws_cap = 0;                // bytes of the forward's level windows (chunking of the groups)
+    int64_t ws_limit = 0;              // cos_set_workspace_limit when planned (0: share of free memory)
     int32_t nconf = 0, nflav = 0, variant = 0, flags = 0;
     int nfs = 1, nmat = 1, nstub = 1;
     bool uniform_n = true;
@@ -361,6 +427,7 @@ struct cos_batch_s {
     int64_t win_doubles = 0;
     // reverse sweep (allocated on first use)
     double *d_Fall = nullptr, *d_GbT = nullptr, *d_sbT = nullptr;
+    double *d_Gpart = nullptr, *d_Spart = nullptr;   // deterministic reverse: per-part partial sums
     int64_t fall_doubles = 0;
     // phase timing: events recorded at phase boundaries since the last read,
     // each labelled with the phase that starts there (-1: end of a call)
@@ -368,6 +435,7 @@ struct cos_batch_s {
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_phase;
     bool counted = false;              // included in g_live
+    int adj_segments = 0;              // 0 automatic, 1 store every forward level, 2 two segments
 };
 
 namespace {
@@ -514,7 +582,12 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
     std::unique_ptr<cos_batch_s, Del> b(new cos_batch_s());
     b->dev = dev;
     b->ncu = ncu;
-    b->ws_cap = g_ws_limit.load() > 0 ? g_ws_limit.load() : mem / 3;
+    // the forward's level windows take up to 45% of the free memory; the
+    // reverse sweep's stored levels (made at its first call) up to 90% of what
+    // is free then
+    b->ws_limit = g_ws_limit.load();
+    b->ws_cap = workspace_cap(b->ws_limit, 0.45);
+    if (b->ws_cap <= 0) b->ws_cap = mem / 3;
     b->nconf = nconf;
     b->nflav = nflav;
     b->variant = variant;
@@ -534,7 +607,7 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
     std::vector<int32_t> order(nconf);
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return n[a] > n[c]; });
-    int64_t gt = 0, sg = 0, ln = 0, win = 0;
+    int64_t gt = 0, sg = 0, ln = 0;
     for (int i = 0; i < nconf;) {
         int j = i;
         while (j < nconf && n[order[j]] == n[order[i]]) ++j;
@@ -552,23 +625,34 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
             std::lock_guard<std::mutex> lk(g_mu);
             o.hp = host_plan(o.n, sub);
         }
-        const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
-        const int64_t per_group = 2 * (int64_t)o.hp->max_rows * rs;
-        o.chunk_fwd = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, b->ws_cap / (8 * per_group)));
-        win = std::max(win, per_group * o.chunk_fwd);
         gt += (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
         sg += (int64_t)o.ngroups * b->nfs * 64;
         ln += (int64_t)o.ngroups * 64;
         b->orders.push_back(o);
         i = j;
     }
-    b->win_doubles = win;
-    if (hipMalloc((void **)&b->d_order, sizeof(int32_t) * nconf) != hipSuccess ||
-        hipMalloc((void **)&b->d_GT, sizeof(double) * gt) != hipSuccess ||
-        hipMalloc((void **)&b->d_sigT, sizeof(double) * sg) != hipSuccess ||
-        hipMalloc((void **)&b->d_lane, sizeof(int32_t) * ln) != hipSuccess ||
-        hipMalloc((void **)&b->d_win, sizeof(double) * win) != hipSuccess)
-        return fail(COS_ENOMEM, "workspace allocation failed (%.1f MB)", 8.0 * (gt + sg + win) / 1e6);
+    if (dev_malloc((void **)&b->d_order, sizeof(int32_t) * nconf) != hipSuccess ||
+        dev_malloc((void **)&b->d_GT, sizeof(double) * gt) != hipSuccess ||
+        dev_malloc((void **)&b->d_sigT, sizeof(double) * sg) != hipSuccess ||
+        dev_malloc((void **)&b->d_lane, sizeof(int32_t) * ln) != hipSuccess)
+        return fail(COS_ENOMEM, "workspace allocation failed (%.1f MB)", 8.0 * (gt + sg) / 1e6);
+    {
+        // two level windows per group of the chunk
+        std::vector<int> chunks(b->orders.size()), ng(b->orders.size());
+        for (size_t i = 0; i < b->orders.size(); ++i) ng[i] = b->orders[i].ngroups;
+        auto per_group = [&](size_t i) {
+            const OrderGroup &o = b->orders[i];
+            return 2 * (int64_t)o.hp->max_rows * b->nfs * o.slots() * 64;
+        };
+        auto total = [&]() {
+            int64_t w = 0;
+            for (size_t i = 0; i < chunks.size(); ++i) w = std::max(w, per_group(i) * chunks[i]);
+            return w;
+        };
+        if ((st = alloc_chunked(&b->d_win, chunks, ng, b->ws_cap, per_group, total, "level window"))) return st;
+        for (size_t i = 0; i < chunks.size(); ++i) b->orders[i].chunk_fwd = chunks[i];
+        b->win_doubles = total();
+    }
     HIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nconf, hipMemcpyHostToDevice));
     {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -589,6 +673,8 @@ cos_status cos_batch_destroy(cos_batch_t b) {
     (void)hipFree(b->d_Fall);
     (void)hipFree(b->d_GbT);
     (void)hipFree(b->d_sbT);
+    (void)hipFree(b->d_Gpart);
+    (void)hipFree(b->d_Spart);
     for (hipEvent_t e : b->ev) (void)hipEventDestroy(e);
     if (b->counted) {
         std::lock_guard<std::mutex> lk(g_mu);
@@ -663,19 +749,23 @@ static int fwd_masks(const LaunchShape &sh, int nfs, int nm, int ng, int ncu) {
 }
 
 // masks per wavefront of a reverse level launch: one workgroup (16
-// wavefronts, one per CU by its LDS footprint) flushes its dS/dG accumulator
-// once per flavour, so blocks should be large, but a level needs several
-// workgroups per CU or its last round leaves most of the chip idle
+// wavefronts, one per CU by its LDS footprint) loads G and flushes its dS/dG
+// accumulator once per flavour, so blocks should be large; its wavefronts
+// share the block's masks dynamically, so workgroups take equal time, and the
+// level is cut into as few rounds of one workgroup per CU as the cap allows,
+// with the masks spread evenly over them
 static int adj_masks(const LaunchShape &sh, int nm, int ng, int ncu) {
-    const int64_t per = ((int64_t)nm * ng) / std::max<int64_t>(1, (int64_t)ncu * 16 * 4);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(sh.adj_cap, per));
+    const int64_t slots = (int64_t)std::max(1, ncu) * 16;                 // wavefronts of one round (16 per CU)
+    const int64_t work = (int64_t)nm * ng;
+    const int64_t rounds = std::max<int64_t>(1, (work + slots * sh.adj_cap - 1) / (slots * sh.adj_cap));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(sh.adj_cap, (work + slots * rounds - 1) / (slots * rounds)));
 }
 
 // forward levels of one order, all groups, chunk by chunk (two level windows)
 static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double *d_G, const int64_t *d_Goff,
                                 const double *d_stub, double cycle_weight, double *d_out, hipStream_t s) {
     HIP_TRY(tmark(b, COS_PHASE_PACK, s));
-    HIP_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
+    LAUNCH_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
     HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
     const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
     const int64_t gstride = (int64_t)o.hp->max_rows * rs;
@@ -693,8 +783,8 @@ static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double
             const int nm = o.hp->levels[l].w;
             a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
             a.out = d_out;
-            if (o.sub) HIP_TRY(launch_sub_level(a, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
-            else HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            if (o.sub) LAUNCH_TRY(launch_sub_level(a, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            else LAUNCH_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
         }
     }
     return COS_OK;
@@ -714,94 +804,196 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
     return COS_OK;
 }
 
+// rows of levels a..c (inclusive) of a plan
+static int64_t level_rows(const HostPlan &p, int a, int c) { return (int64_t)p.levels[c + 1].x - p.levels[a].x; }
+
+// the split level h of a two-segment reverse sweep that minimises the larger
+// segment (levels 1..h, recomputed, or h+1..2n, stored by the first forward)
+static int best_split(const HostPlan &p, int n) {
+    int best = 0;
+    int64_t bv = INT64_MAX;
+    for (int h = 1; h < 2 * n; ++h) {
+        const int64_t v = std::max(level_rows(p, 1, h), level_rows(p, h + 1, 2 * n));
+        if (v < bv) bv = v, best = h;
+    }
+    return best;
+}
+
+// forward-state rows the reverse sweep of one group keeps
+static int64_t adj_store_rows(const HostPlan &p, int n, int h) {
+    return h ? std::max(level_rows(p, 1, h), level_rows(p, h + 1, 2 * n)) : (int64_t)p.rows.size();
+}
+
 static cos_status prepare_adjoint(cos_batch_t b) {
     if (b->d_Fall) return COS_OK;
-    int64_t fall = 0, gb = 0, sb = 0;
+    int64_t gb = 0, sb = 0, sp = 0;
     for (OrderGroup &o : b->orders) {
-        const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
-        // all forward levels and two adjoint windows
-        const int64_t per_group = ((int64_t)o.hp->rows.size() + 2 * (int64_t)o.hp->max_rows) * rs;
-        o.chunk_adj = (int)std::max<int64_t>(1, std::min<int64_t>(o.ngroups, b->ws_cap / (8 * per_group)));
-        fall = std::max(fall, per_group * o.chunk_adj);
         o.gb_off = gb;
         o.sb_off = sb;
+        o.sp_off = sp;
         gb += (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
         sb += (int64_t)o.ngroups * b->nfs * 64;
+        sp += (int64_t)kDetParts * o.ngroups * b->nfs * o.slots() * 64;
     }
-    if (hipMalloc((void **)&b->d_Fall, sizeof(double) * fall) != hipSuccess) {
-        b->d_Fall = nullptr;
-        return fail(COS_ENOMEM, "reverse-sweep workspace allocation failed (%.1f MB)", 8.0 * fall / 1e6);
-    }
-    if (hipMalloc((void **)&b->d_GbT, sizeof(double) * gb) != hipSuccess ||
-        hipMalloc((void **)&b->d_sbT, sizeof(double) * sb) != hipSuccess) {
-        (void)hipFree(b->d_Fall);
+    const bool det = (b->flags & COS_F_DETERMINISTIC) != 0;
+    if (dev_malloc((void **)&b->d_GbT, sizeof(double) * gb) != hipSuccess ||
+        dev_malloc((void **)&b->d_sbT, sizeof(double) * sb) != hipSuccess ||
+        (det && (dev_malloc((void **)&b->d_Gpart, sizeof(double) * kDetParts * gb) != hipSuccess ||
+                 dev_malloc((void **)&b->d_Spart, sizeof(double) * sp) != hipSuccess))) {
         (void)hipFree(b->d_GbT);
-        b->d_Fall = b->d_GbT = nullptr;
+        (void)hipFree(b->d_sbT);
+        (void)hipFree(b->d_Gpart);
+        b->d_GbT = b->d_sbT = b->d_Gpart = b->d_Spart = nullptr;
         return fail(COS_ENOMEM, "gradient accumulator allocation failed");
     }
-    b->fall_doubles = fall;
+    // all forward levels and two adjoint windows per group of the chunk, in
+    // at most 90% of the memory free now (or the caller's bound)
+    int64_t cap = workspace_cap(b->ws_limit, 0.9);
+    if (cap <= 0) cap = b->ws_cap;
+    // two segments (about 40% less memory, the lower levels computed twice)
+    // when asked for, or when storing every level would split the groups
+    for (OrderGroup &o : b->orders) {
+        const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
+        const int64_t all = ((int64_t)o.hp->rows.size() + 2 * (int64_t)o.hp->max_rows) * rs;
+        const bool seg = o.n >= 3 && (b->adj_segments == 2 ||
+                                      (b->adj_segments == 0 && cap / (8 * all) < o.ngroups));
+        o.adj_split = seg ? best_split(*o.hp, o.n) : 0;
+    }
+    std::vector<int> chunks(b->orders.size()), ng(b->orders.size());
+    for (size_t i = 0; i < b->orders.size(); ++i) ng[i] = b->orders[i].ngroups;
+    auto per_group = [&](size_t i) {
+        const OrderGroup &o = b->orders[i];
+        return (adj_store_rows(*o.hp, o.n, o.adj_split) + 2 * (int64_t)o.hp->max_rows) * b->nfs * o.slots() * 64;
+    };
+    auto total = [&]() {
+        int64_t w = 0;
+        for (size_t i = 0; i < chunks.size(); ++i) w = std::max(w, per_group(i) * chunks[i]);
+        return w;
+    };
+    if (cos_status st = alloc_chunked(&b->d_Fall, chunks, ng, cap, per_group, total, "reverse-sweep workspace")) {
+        (void)hipFree(b->d_GbT);
+        (void)hipFree(b->d_sbT);
+        (void)hipFree(b->d_Gpart);
+        (void)hipFree(b->d_Spart);
+        b->d_GbT = b->d_sbT = b->d_Gpart = b->d_Spart = nullptr;
+        return st;
+    }
+    for (size_t i = 0; i < chunks.size(); ++i) b->orders[i].chunk_adj = chunks[i];
+    b->fall_doubles = total();
     return COS_OK;
 }
 
 // forward (every level kept) and reverse levels of one order
+// forward (levels kept) and reverse levels of one order.  Every forward level
+// is stored, or with a split level h only levels h+1..2n: their reverse runs
+// first, then levels 1..h are computed again into the same store and
+// reversed (the adjoint windows keep B(h+1) meanwhile)
 static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double *d_G, const int64_t *d_Goff,
                                 const double *d_stub, double cycle_weight, const double *d_out_bar,
                                 double *d_out, double *d_G_bar, double *d_stub_bar, hipStream_t s) {
     const PackArgs pa = pack_args(b, o, d_G, d_Goff, d_stub);
     HIP_TRY(tmark(b, COS_PHASE_PACK, s));
-    HIP_TRY(launch_pack(pa, s));
+    LAUNCH_TRY(launch_pack(pa, s));
     double *GbT = b->d_GbT + o.gb_off, *sbT = b->d_sbT + o.sb_off;
     const int64_t ngb = (int64_t)o.ngroups * b->nfs * o.slots() * o.slots() * 64;
     const int64_t nsb = (int64_t)o.ngroups * b->nfs * 64;
-    HIP_TRY(launch_zero(GbT, ngb, s));
-    HIP_TRY(launch_zero(sbT, nsb, s));
+    const bool det = (b->flags & COS_F_DETERMINISTIC) != 0;
+    double *Gp = det ? b->d_Gpart + (int64_t)kDetParts * o.gb_off : nullptr;
+    double *Sp = det ? b->d_Spart + o.sp_off : nullptr;
+    const int64_t nsp = (int64_t)kDetParts * o.ngroups * b->nfs * o.slots() * 64;
+    if (det) {
+        LAUNCH_TRY(launch_zero(Gp, (int64_t)kDetParts * ngb, s));
+        LAUNCH_TRY(launch_zero(Sp, nsp, s));
+    } else {
+        LAUNCH_TRY(launch_zero(GbT, ngb, s));
+        LAUNCH_TRY(launch_zero(sbT, nsb, s));
+    }
+    const int n2 = 2 * o.n, h = o.adj_split;
     const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
-    const int64_t total_rows = (int64_t)o.hp->rows.size();
-    const int64_t fstride = total_rows * rs, bstride = (int64_t)o.hp->max_rows * rs;
+    const int64_t srows = adj_store_rows(*o.hp, o.n, h), mrows = o.hp->max_rows;
+    const int64_t fstride = srows * rs, bstride = mrows * rs;
+    // store row of level l: levels are stored from level 1 (all, or the lower
+    // segment) or from level h + 1 (the upper segment)
+    auto srow = [&](int l, bool upper) { return o.hp->levels[l].x - (upper ? o.hp->levels[h + 1].x : 0); };
     for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_adj) {
         const int cg = std::min(o.chunk_adj, o.ngroups - c0);
-        double *Fall = b->d_Fall;
-        double *B0 = Fall + fstride * cg, *B1 = B0 + bstride * cg;
+        double *Fs = b->d_Fall;
+        double *B0 = Fs + fstride * cg, *B1 = B0 + bstride * cg;
+        // forward from level `from` to `to`: reads level l, writes level l + 1;
+        // stored levels in Fs, the others (below the upper segment, first
+        // pass only) in the adjoint windows, which are free until the reverse
+        auto forward = [&](int from, int to, bool first_pass) -> cos_status {
+            for (int l = from; l <= to; ++l) {
+                LvlArgs a = level_args(b, o, cycle_weight);
+                a.level = l;
+                a.group0 = c0;
+                const bool in_store = !first_pass || !h || l > h;      // level l
+                const bool out_store = !first_pass || !h || l + 1 > h; // level l + 1
+                const bool up = first_pass && h;
+                a.cur = in_store ? Fs : ((l & 1) ? B1 : B0);
+                a.cur_gstride = in_store ? fstride : bstride;
+                a.cur_frows = in_store ? srows : mrows;
+                a.cur_row0 = in_store ? (int32_t)srow(l, up) : 0;
+                a.nxt = out_store ? Fs : (((l + 1) & 1) ? B1 : B0);
+                a.nxt_gstride = out_store ? fstride : bstride;
+                a.nxt_frows = out_store ? srows : mrows;
+                a.nxt_row0 = out_store ? (int32_t)srow(std::min(l + 1, n2 + 1), up) : 0;
+                const int nm = o.hp->levels[l].w;
+                a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
+                a.out = d_out;
+                if (o.sub) LAUNCH_TRY(launch_sub_level(a, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+                else LAUNCH_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
+            }
+            return COS_OK;
+        };
+        auto reverse = [&](int from, int to, bool upper) -> cos_status {
+            for (int l = from; l >= to; --l) {
+                LvlArgs a = level_args(b, o, cycle_weight);
+                a.level = l;
+                a.group0 = c0;
+                a.cur = (l & 1) ? B0 : B1;     // adjoints of level + 1
+                a.nxt = (l & 1) ? B1 : B0;     // adjoints of level
+                a.cur_gstride = a.nxt_gstride = bstride;
+                a.cur_frows = a.nxt_frows = mrows;
+                a.F = Fs;
+                a.F_gstride = fstride;
+                a.F_frows = srows;
+                a.F_row0 = (int32_t)srow(l, upper);
+                const int nm = o.hp->levels[l].w;
+                a.mpb = adj_masks(o.shape, nm, cg, b->ncu);
+                a.out_bar = d_out_bar;
+                a.Gbar_T = GbT;
+                a.sbar_T = sbT;
+                a.gacc = o.sub ? 0 : o.shape.adj_gacc;
+                if (det) {
+                    a.Gbar_T = Gp;
+                    a.sbar_T = Sp;
+                    a.det_groups = o.ngroups;
+                    LAUNCH_TRY(launch_level_det(a, cg, s));
+                    continue;
+                }
+                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
+                else LAUNCH_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg,
+                                             o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block(), s));
+            }
+            return COS_OK;
+        };
         HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
-        for (int l = 1; l <= 2 * o.n; ++l) {   // forward, every level kept
-            LvlArgs a = level_args(b, o, cycle_weight);
-            a.level = l;
-            a.group0 = c0;
-            a.cur = a.nxt = Fall;
-            a.cur_gstride = a.nxt_gstride = fstride;
-            a.cur_frows = a.nxt_frows = total_rows;
-            a.cur_row0 = o.hp->levels[l].x;
-            a.nxt_row0 = o.hp->levels[std::min(l + 1, 2 * o.n + 1)].x;
-            const int nm = o.hp->levels[l].w;
-            a.mpb = fwd_masks(o.shape, b->nfs, nm, cg, b->ncu);
-            a.out = d_out;
-            if (o.sub) HIP_TRY(launch_sub_level(a, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
-            else HIP_TRY(launch_level(a, false, (nm + a.mpb - 1) / a.mpb, cg, o.shape.fwd_wpb, s));
-        }
+        if (cos_status st = forward(1, n2, true)) return st;
         HIP_TRY(tmark(b, COS_PHASE_REVERSE, s));
-        for (int l = 2 * o.n; l >= 1; --l) {   // reverse
-            LvlArgs a = level_args(b, o, cycle_weight);
-            a.level = l;
-            a.group0 = c0;
-            a.cur = (l & 1) ? B0 : B1;         // adjoints of level + 1
-            a.nxt = (l & 1) ? B1 : B0;         // adjoints of level
-            a.cur_gstride = a.nxt_gstride = bstride;
-            a.cur_frows = a.nxt_frows = o.hp->max_rows;
-            a.F = Fall;
-            a.F_gstride = fstride;
-            a.F_frows = total_rows;
-            a.F_row0 = o.hp->levels[l].x;
-            const int nm = o.hp->levels[l].w;
-            a.mpb = adj_masks(o.shape, nm, cg, b->ncu);
-            a.out_bar = d_out_bar;
-            a.Gbar_T = GbT;
-            a.sbar_T = sbT;
-            if (o.sub) HIP_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
-            else HIP_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
+        if (cos_status st = reverse(n2, h + 1, h != 0)) return st;
+        if (h) {
+            // level 1 is the start state, which the kernels form themselves
+            HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
+            if (cos_status st = forward(1, h - 1, false)) return st;
+            HIP_TRY(tmark(b, COS_PHASE_REVERSE, s));
+            if (cos_status st = reverse(h, 1, false)) return st;
         }
     }
     HIP_TRY(tmark(b, COS_PHASE_UNPACK, s));
-    HIP_TRY(launch_unpack(pa, GbT, sbT, d_G_bar, (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr, s));
+    if (det)
+        LAUNCH_TRY(launch_det_reduce(Gp, (b->flags & COS_F_STUBS) ? Sp : nullptr, ngb, nsb, o.slots(), GbT, sbT, s));
+    LAUNCH_TRY(launch_unpack(pa, GbT, sbT, d_G_bar, (b->flags & COS_F_STUBS) ? d_stub_bar : nullptr, s));
     return COS_OK;
 }
 
@@ -874,7 +1066,7 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
     b->timing = false;
     static const int kWaves[] = {4, 8}, kSubWaves[] = {8, 16};
     static const int kCaps[] = {1, 2, 4, 8, 16};
-    static const int kAdjCaps[] = {1, 2, 4, 6, 7, 8, 10, 12, 16};
+    static const int kAdjCaps[] = {2, 4, 6, 8, 12, 16, 24, 32};
     for (OrderGroup &o : b->orders) {
         // forward: waves per workgroup x masks per wavefront
         LaunchShape best = o.shape;
@@ -890,17 +1082,32 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
             }
         o.shape = best;
         if (st) break;
-        if (!d_out_bar) continue;
-        // reverse: masks per wavefront (the forward part is the same for every candidate)
+        if (!d_out_bar || (b->flags & COS_F_DETERMINISTIC)) continue;   // the deterministic reverse has one shape
+        // reverse: accumulator (LDS, or global atomics with 8 or 16 wavefronts
+        // per workgroup; the labelled kernels keep LDS) x masks per wavefront
+        // (the forward part is the same for every candidate)
         tbest = 1e30f;
-        for (int cap : kAdjCaps) {
-            o.shape.adj_cap = cap;
-            float t;
-            st = time_best(s, 3, [&] {
-                return adjoint_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar, d_stub_bar, s);
-            }, &t);
+        static const int kAdjVariants[][2] = {{0, 16}, {1, 8}, {1, 16}};   // {global atomics, wavefronts}
+        for (const auto &var : kAdjVariants) {
+            if (o.sub && var[0]) continue;
+            for (int cap : kAdjCaps) {
+                o.shape.adj_gacc = var[0];
+                o.shape.adj_wpb = var[1];
+                o.shape.adj_cap = cap;
+                float t;
+                st = time_best(s, 3, [&] {
+                    return adjoint_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar,
+                                         d_stub_bar, s);
+                }, &t);
+                if (st) break;
+                if (t < tbest) {
+                    tbest = t;
+                    best.adj_cap = cap;
+                    best.adj_gacc = var[0];
+                    best.adj_wpb = var[1];
+                }
+            }
             if (st) break;
-            if (t < tbest) { tbest = t; best.adj_cap = cap; }
         }
         o.shape = best;
         if (st) break;
@@ -935,11 +1142,38 @@ cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_wave
         if (o.n == n) {
             const int wmax = o.sub ? 16 : 8;
             if (fwd_waves < 1 || fwd_waves > wmax) return fail(COS_EINVAL, "fwd_waves must be in [1, %d]", wmax);
-            if (fwd_masks < 1 || fwd_masks > 16 || adj_masks < 1 || adj_masks > 16)
-                return fail(COS_EINVAL, "fwd_masks and adj_masks must be in [1, 16]");
+            if (fwd_masks < 1 || fwd_masks > 16 || adj_masks < 1 || adj_masks > 64)
+                return fail(COS_EINVAL, "fwd_masks must be in [1, 16] and adj_masks in [1, 64]");
             o.shape.fwd_wpb = fwd_waves;
             o.shape.fwd_cap = fwd_masks;
             o.shape.adj_cap = adj_masks;
+            return COS_OK;
+        }
+    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
+}
+
+cos_status cos_batch_reverse_variant(cos_batch_t b, int32_t n, int32_t *global_atomics, int32_t *waves) {
+    if (!b || !global_atomics || !waves) return fail(COS_EINVAL, "null argument");
+    for (const OrderGroup &o : b->orders)
+        if (o.n == n) {
+            *global_atomics = o.shape.adj_gacc;
+            *waves = o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block();
+            return COS_OK;
+        }
+    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
+}
+
+cos_status cos_batch_set_reverse_variant(cos_batch_t b, int32_t n, int32_t global_atomics, int32_t waves) {
+    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    if (global_atomics != 0 && global_atomics != 1) return fail(COS_EINVAL, "global_atomics must be 0 or 1");
+    if (global_atomics ? (waves < 1 || waves > 16) : waves != adj_waves_per_block())
+        return fail(COS_EINVAL, "waves must be in [1, 16] with global atomics, %d with the LDS accumulator",
+                    adj_waves_per_block());
+    for (OrderGroup &o : b->orders)
+        if (o.n == n) {
+            if (o.sub && global_atomics) return fail(COS_EINVAL, "labelled batches keep the LDS accumulator");
+            o.shape.adj_gacc = global_atomics;
+            o.shape.adj_wpb = waves;
             return COS_OK;
         }
     return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
@@ -984,7 +1218,7 @@ cos_status cos_connected_sum(int32_t n, int32_t nflav, int32_t variant, int32_t 
     const size_t side = (flags & COS_F_SUBLATTICE) ? 2 * (size_t)n : (size_t)n;
     const size_t ng = (size_t)b->nmat * side * side;
     double *d = nullptr;
-    if (hipMalloc((void **)&d, sizeof(double) * (ng + COS_FMAX + 1)) != hipSuccess) {
+    if (dev_malloc((void **)&d, sizeof(double) * (ng + COS_FMAX + 1)) != hipSuccess) {
         cos_batch_destroy(b);
         return fail(COS_ENOMEM, "device allocation failed");
     }
@@ -1009,7 +1243,7 @@ cos_status cos_build_g0(int32_t nconf, const int32_t *d_n, const int64_t *d_voff
     if (L < 1 || L > 32) return fail(COS_ERANGE, "L must be in [1, 32], got %d", L);
     if (nmat < 1 || nmat > COS_FMAX) return fail(COS_ERANGE, "nmat must be in [1, %d]", COS_FMAX);
     if (!(beta > 0.0)) return fail(COS_ERANGE, "beta must be positive");
-    HIP_TRY(launch_g0(nconf, d_n, d_voff, d_sites, d_tau, L, t, beta, nmat, mu, alpha, d_Goff, d_G, d_dG,
+    LAUNCH_TRY(launch_g0(nconf, d_n, d_voff, d_sites, d_tau, L, t, beta, nmat, mu, alpha, d_Goff, d_G, d_dG,
                       (hipStream_t)stream));
     return COS_OK;
 }
@@ -1024,7 +1258,7 @@ cos_status cos_build_g0_honeycomb(int32_t nconf, const int32_t *d_n, const int64
     if (L < 1 || L > 32) return fail(COS_ERANGE, "L must be in [1, 32], got %d", L);
     if (nmat < 1 || nmat > COS_FMAX) return fail(COS_ERANGE, "nmat must be in [1, %d]", COS_FMAX);
     if (!(beta > 0.0)) return fail(COS_ERANGE, "beta must be positive");
-    HIP_TRY(launch_g0_honeycomb(nconf, d_n, d_voff, d_cells, d_tau, L, t, beta, nmat, mu, alpha, delta, d_Goff,
+    LAUNCH_TRY(launch_g0_honeycomb(nconf, d_n, d_voff, d_cells, d_tau, L, t, beta, nmat, mu, alpha, delta, d_Goff,
                                 d_G, d_dG, (hipStream_t)stream));
     return COS_OK;
 }
@@ -1038,7 +1272,7 @@ cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat, c
     if (nmat < 1 || nmat > COS_FMAX) return fail(COS_ERANGE, "nmat must be in [1, %d]", COS_FMAX);
     if (d_stub_bar && nstub != 1 && nstub != nmat) return fail(COS_EINVAL, "nstub must be 1 or nmat");
     if (d_stub_bar && U == 0.0) return fail(COS_EINVAL, "U must be nonzero");
-    HIP_TRY(launch_chain(nconf, d_n, nmat, d_Goff, d_G_bar, d_dG, d_stub_bar, nstub, U, d_mu_bar, d_alpha_bar,
+    LAUNCH_TRY(launch_chain(nconf, d_n, nmat, d_Goff, d_G_bar, d_dG, d_stub_bar, nstub, U, d_mu_bar, d_alpha_bar,
                          (hipStream_t)stream));
     return COS_OK;
 }
@@ -1050,7 +1284,7 @@ cos_status cos_mc_sample(int32_t nconf, int32_t n, int32_t L, double beta, uint6
     if (L < 1 || L > 32) return fail(COS_ERANGE, "L must be in [1, 32], got %d", L);
     if (!(beta > 0.0)) return fail(COS_ERANGE, "beta must be positive");
     if (first < 0) return fail(COS_EINVAL, "first must be >= 0");
-    HIP_TRY(launch_mc_sample(nconf, n, L, beta, seed, first, d_sites, d_tau, (hipStream_t)stream));
+    LAUNCH_TRY(launch_mc_sample(nconf, n, L, beta, seed, first, d_sites, d_tau, (hipStream_t)stream));
     return COS_OK;
 }
 
@@ -1072,13 +1306,13 @@ cos_status cos_cdet_su2(int32_t nconf, int32_t n, const double *d_A, int32_t pre
     if (work_bytes < need) return fail(COS_EINVAL, "workspace too small: %llu bytes, need %llu",
                                        (unsigned long long)work_bytes, (unsigned long long)need);
     if (!(eps >= 0.0)) return fail(COS_EINVAL, "eps must be >= 0");
-    HIP_TRY(launch_cdet(nconf, n, d_A, precision, eps, d_work, d_out, (hipStream_t)stream));
+    LAUNCH_TRY(launch_cdet(nconf, n, d_A, precision, eps, d_work, d_out, (hipStream_t)stream));
     return COS_OK;
 }
 
 cos_status cos_accumulate_moments(int32_t count, const double *d_x, double *d_acc, void *stream) {
     if (count < 1 || !d_x || !d_acc) return fail(COS_EINVAL, "count >= 1 and device buffers are required");
-    HIP_TRY(launch_moments(count, d_x, d_acc, (hipStream_t)stream));
+    LAUNCH_TRY(launch_moments(count, d_x, d_acc, (hipStream_t)stream));
     return COS_OK;
 }
 
@@ -1157,6 +1391,48 @@ cos_status cos_pade(int32_t m, int32_t k, const double *a, double x, double *val
             ac[j] = a[j];
         }
     }
+    return COS_OK;
+}
+
+cos_status cos_batch_set_adjoint_segments(cos_batch_t b, int32_t segments) {
+    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    if (segments < 0 || segments > 2) return fail(COS_EINVAL, "segments must be 0, 1 or 2, got %d", segments);
+    if (cos_status st = check_batch_device(b)) return st;
+    b->adj_segments = segments;
+    // the reverse-sweep workspace is planned again at the next reverse call
+    if (b->d_Fall) {
+        HIP_TRY(hipDeviceSynchronize());
+        (void)hipFree(b->d_Fall);
+        (void)hipFree(b->d_GbT);
+        (void)hipFree(b->d_sbT);
+        (void)hipFree(b->d_Gpart);
+        (void)hipFree(b->d_Spart);
+        b->d_Fall = b->d_GbT = b->d_sbT = b->d_Gpart = b->d_Spart = nullptr;
+    }
+    return COS_OK;
+}
+
+cos_status cos_batch_adjoint_plan(cos_batch_t b, int32_t n, int32_t *split_level, int32_t *groups_per_chunk,
+                                  int64_t *bytes_per_group) {
+    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
+    if (!b->d_Fall) return fail(COS_EINVAL, "no reverse call has planned the reverse-sweep workspace yet");
+    for (const OrderGroup &o : b->orders)
+        if (o.n == n) {
+            if (split_level) *split_level = o.adj_split;
+            if (groups_per_chunk) *groups_per_chunk = o.chunk_adj;
+            if (bytes_per_group)
+                *bytes_per_group = 8 * (adj_store_rows(*o.hp, o.n, o.adj_split) + 2 * (int64_t)o.hp->max_rows) *
+                                   b->nfs * o.slots() * 64;
+            return COS_OK;
+        }
+    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
+}
+
+cos_status cos_inject_failures(int32_t kind, int32_t skip, int32_t count) {
+    if (kind != 0 && kind != 1) return fail(COS_EINVAL, "kind must be 0 (device allocation) or 1 (kernel launch)");
+    if (skip < 0 || count < 0) return fail(COS_EINVAL, "skip and count must be >= 0");
+    g_inj_skip[kind].store(skip);
+    g_inj_count[kind].store(count);
     return COS_OK;
 }
 
@@ -1258,6 +1534,6 @@ cos_status libcos::forward_fixed(int dev, int ncu, const FixedWorkspace &ws, int
         std::lock_guard<std::mutex> lk(g_mu);
         o.hp = host_plan(n);
     }
-    HIP_TRY(launch_iota(ws.order, nconf, s));
+    LAUNCH_TRY(launch_iota(ws.order, nconf, s));
     return forward_order(&b, o, d_G, nullptr, d_stub, cycle_weight, d_out, s);
 }

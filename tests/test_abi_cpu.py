@@ -82,7 +82,8 @@ def test_argument_validation_without_device(B):
     assert lib.cos_batch_create(2, n.ctypes.data, 0, 0, 0, ctypes.byref(h)) == -2
     assert lib.cos_batch_create(2, n.ctypes.data, 17, 0, 0, ctypes.byref(h)) == -2
     assert lib.cos_batch_create(2, n.ctypes.data, 2, 7, 0, ctypes.byref(h)) == -1
-    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 8, ctypes.byref(h)) == -1
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 16, ctypes.byref(h)) == -1
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 10, ctypes.byref(h)) == -1  # deterministic + labels
     assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 3, ctypes.byref(h)) == -1   # shifts with sublattices
     big = np.array([4, 9], dtype=np.int32)
     assert lib.cos_batch_create(2, big.ctypes.data, 2, 0, 2, ctypes.byref(h)) == -2  # above the sublattice max
@@ -91,7 +92,7 @@ def test_argument_validation_without_device(B):
     assert lib.cos_batch_create(2, n.ctypes.data, 2, 0, 4, ctypes.byref(h)) == -1   # uniform variant
     assert lib.cos_batch_create(2, n.ctypes.data, 3, 1, 4, ctypes.byref(h)) == -1   # three flavours
     assert lib.cos_batch_create(2, n.ctypes.data, 2, 1, 5, ctypes.byref(h)) == -1   # with shifts
-    assert lib.cos_batch_create(2, n.ctypes.data, 2, 1, 8, ctypes.byref(h)) == -1   # unknown flag
+    assert lib.cos_batch_create(2, n.ctypes.data, 2, 1, 20, ctypes.byref(h)) == -1  # unknown flag
     assert lib.cos_plan_counts_mask_only(13, 0, None, None, None) == -2
     assert lib.cos_plan_counts_mask_only(9, 2, None, None, None) == -2
     assert lib.cos_plan_counts_mask_only(4, 1, None, None, None) == -1
@@ -124,6 +125,11 @@ def test_argument_validation_without_device(B):
     assert st(4, 4, 2, 1, 0, None, None, -1.0, G.ctypes.data, None) == -1
     assert "orders 1..8" in (st(4, 9, 2, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None),
                              lib.cos_last_error().decode())[1]
+    # failure injection: kinds 0 (device allocation) and 1 (kernel launch) only
+    assert lib.cos_inject_failures(2, 0, 1) == -1
+    assert lib.cos_inject_failures(0, -1, 1) == -1
+    assert lib.cos_inject_failures(1, 0, -1) == -1
+    assert lib.cos_inject_failures(0, 0, 0) == 0 and lib.cos_inject_failures(1, 0, 0) == 0
     assert _st(B, 0) == "ok" and _st(B, -2) == "argument out of range"
 
 

@@ -209,7 +209,9 @@ def test_autotune_keeps_results():
     shapes = {k: b.launch_shape(k) for k in (4, 7, 9)}
     for k, sh in shapes.items():
         assert sh["fwd_waves"] in (4, 8) and sh["fwd_masks"] in (1, 2, 4, 8, 16), sh
-        assert sh["adj_masks"] in (1, 2, 4, 6, 7, 8, 10, 12, 16), sh
+        assert sh["adj_masks"] in (2, 4, 6, 8, 12, 16, 24, 32), sh
+        assert b.reverse_variant(k) in ({"global_atomics": 0, "waves": 16}, {"global_atomics": 1, "waves": 8},
+                                        {"global_atomics": 1, "waves": 16}), b.reverse_variant(k)
     with pytest.raises(B.CosError):
         b.launch_shape(5)
     S2 = torch.full_like(S0, float("nan"))
@@ -270,7 +272,7 @@ def test_set_launch_shape_keeps_sums():
         b.forward(G, Goff, None, -1.0, out)
         torch.cuda.synchronize()
         assert torch.equal(out, ref), (waves, masks)
-    for bad in ((0, 4, 4), (9, 4, 4), (8, 0, 4), (8, 4, 17)):
+    for bad in ((0, 4, 4), (9, 4, 4), (8, 0, 4), (8, 17, 4), (8, 4, 65)):
         with pytest.raises(B.CosError):
             b.set_launch_shape(5, *bad)
     with pytest.raises(B.CosError):
