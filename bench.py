@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12           # MI355X FP64 vector peak, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, bytes/s
-REV_KERNEL = "level_adj_kernel<%d, false>"
+REV_KERNEL = "level_adj_kernel<%d, false, %s>"   # order, mask-only, global atomics
 WORKLOAD = "adjoint"
 
 
@@ -330,7 +330,7 @@ def _cpu_forward_rate(d, idx, threads, variant, nflav, stubs_of):
     return len(idx) / dt, dt
 
 
-def workload_legs(B, torch, reps, cpu_threads=0):
+def workload_legs(B, torch, reps, cpu_threads=0, only=None):
     """The other workloads of the measurement plan, forward sums on the GPU
     with inputs resident (propagator kernel + batched levels), autotuned:
       plain_single  (4x4, beta=2, SU(2), n=4, 1 config): plain call latency
@@ -350,6 +350,8 @@ def workload_legs(B, torch, reps, cpu_threads=0):
         return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     for name in ("plain_single", "plain_batch", "sym_broken", "uneven"):
+        if only and name != only:
+            continue
         d = draw(name)
         w = d.workload
         nmat = w.nflav if w.variant == 1 else 1
@@ -420,6 +422,26 @@ def workload_legs(B, torch, reps, cpu_threads=0):
                     "frac_of_fp64_peak": flop / (lv_ms * 1e-3) / PEAK_FP64,
                     "launch_shapes": {int(k): b.launch_shape(int(k)) for k in np.unique(d.n)}})
         S_host = S.cpu().numpy()
+        if name in ("plain_batch", "sym_broken"):
+            # forward + reverse sweep (the adjoint call, reverse launch shapes autotuned too)
+            ob = torch.ones(nconf, dtype=torch.float64, device=dev)
+            Gb = torch.empty_like(G)
+            sb = None if st is None else torch.empty_like(st)
+            Sa = torch.empty_like(S)
+            b.autotune(G, geo.Goff, st, -1.0, Sa, ob, Gb, sb, stream=stream)
+            b.adjoint(G, geo.Goff, st, -1.0, ob, Sa, Gb, sb, stream)
+            torch.cuda.synchronize()
+            a0, a1 = ev()
+            a0.record(stream)
+            for _ in range(reps):
+                b.adjoint(G, geo.Goff, st, -1.0, ob, Sa, Gb, sb, stream)
+            a1.record(stream)
+            torch.cuda.synchronize()
+            ams = a0.elapsed_time(a1) / reps
+            leg.update({"fwd_adjoint_configs_per_s": nconf / (ams * 1e-3), "fwd_adjoint_ms": ams,
+                        "adjoint_S_equals_forward": bool(torch.equal(Sa, S)),
+                        "reverse_variant": b.reverse_variant(int(d.n[0]))})
+            del Gb, sb, Sa
         if name in ("plain_single", "plain_batch"):
             # the plain form: one call per configuration (2n level launches, one of 64 lanes busy)
             n0 = int(d.n[0])
@@ -527,6 +549,8 @@ def main():
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (plain single, plain batch, symmetry broken, uneven)")
     ap.add_argument("--cpu-sample", type=int, default=1536)
+    ap.add_argument("--leg", choices=("plain_single", "plain_batch", "sym_broken", "uneven"),
+                    help="run only this workload's leg (for profiling; with --counters after the calibration copy)")
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
                          "then exit (for rocprofv3 --pmc passes)")
@@ -542,6 +566,16 @@ def main():
     from paper_2507_12349_amd import _binding as B
     from paper_2507_12349_amd.autograd import Geometry
     from paper_2507_12349_amd.workloads import draw
+
+    if args.leg:
+        if args.counters:
+            src = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+            torch.empty_like(src).copy_(src)
+            torch.cuda.synchronize()
+            del src
+        legs = workload_legs(B, torch, 1 if args.counters else max(3, args.steps // 2), 0, only=args.leg)
+        print(json.dumps({"leg": args.leg, "result": legs[args.leg]}), flush=True)
+        return
 
     d = draw(WORKLOAD, nconf=args.nconf or None)
     w = d.workload
@@ -730,7 +764,9 @@ def main():
     launch_ms = rev_ms / nlaunch                       # average launch
     flop_launch = flop_rev * nconf / nlaunch
     achieved = flop_launch / (launch_ms * 1e-3)
-    traffic = _traffic(REV_KERNEL % n)
+    rev_variant = batch.reverse_variant(n)
+    rev_kernel = REV_KERNEL % (n, "true" if rev_variant["global_atomics"] else "false")
+    traffic = _traffic(rev_kernel)
     hbm = None
     if traffic is not None:
         ai = flop_launch / traffic
@@ -795,7 +831,7 @@ def main():
         "adjoint_plain_check": {"configs": nadj, "S_equals_batched_bitwise": adj_plain_S_equal,
                                 "max_grad_dev_rel_to_max": adj_plain_grad_dev},
         "vs_oracle_refs": _refs_stats(WORKLOAD, S_host) if nconf == 2048 else None,
-        "roofline": {"bound": "alu", "kernel": REV_KERNEL % n,
+        "roofline": {"bound": "alu", "kernel": rev_kernel, "reverse_variant": rev_variant,
                      "note": "bound = the method's: FP64 ALU on algorithmic FLOP; the kernel itself streams every "
                              "DP state through HBM (see hbm: AI ~1 FLOP/B, below the 9.8 FLOP/B ridge), which caps "
                              "frac near AI x 8 TB/s / 78.6 TFLOP/s",
