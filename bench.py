@@ -144,7 +144,8 @@ def honeycomb_forward(B, torch, reps):
     grad = {"configs_per_s": n.size / (a0.elapsed_time(a1) / reps * 1e-3),
             "ms_per_step": a0.elapsed_time(a1) / reps,
             "phases_ms": {k: v / reps for k, v in aph.items()},
-            "kernel": "sub_adj_kernel<8, false>", "launch_shape": ba.launch_shape(nn),
+            "kernel": "sub_adj_kernel<8, false, %s>" % ("true" if ba.reverse_variant(nn)["global_atomics"] else "false"),
+            "launch_shape": ba.launch_shape(nn), "reverse_variant": ba.reverse_variant(nn),
             "S_equals_forward": bool(torch.equal(Sg, S))}
     ba.close()
     mask_only = {"forward_levels_ms": m0.elapsed_time(m1) / reps,
@@ -752,6 +753,28 @@ def main():
     gref = Gb[:nadj * nn]
     adj_plain_grad_dev = float(((Gba - gref).abs().max() / gref.abs().max()).item())
 
+    # the same adjoint call with deterministic gradients (fixed summation order)
+    det_batch = B.Batch(d.n, w.nflav, 0, stubs=True, deterministic=True)
+    Gbd, sbd = torch.empty_like(Gb), torch.empty_like(sb)
+    det_batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gbd, sbd, stream)
+    torch.cuda.synchronize()
+    de0, de1 = evpair()
+    de0.record(stream)
+    for _ in range(reps):
+        det_batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gbd, sbd, stream)
+    de1.record(stream)
+    torch.cuda.synchronize()
+    det_ms = de0.elapsed_time(de1) / reps
+    Gbd2 = torch.empty_like(Gb)
+    det_batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gbd2, sbd, stream)
+    torch.cuda.synchronize()
+    deterministic = {"adjoint_call_ms": det_ms, "adjoint_configs_per_s": nconf / (det_ms * 1e-3),
+                     "slowdown_vs_default_adjoint": det_ms / (acc["adj"] / args.steps),
+                     "repeat_bitwise_equal": bool(torch.equal(Gbd, Gbd2)),
+                     "max_dev_from_default_rel_to_max": float(((Gbd - Gb).abs().max() / Gb.abs().max()).item())}
+    det_batch.close()
+    del Gbd, Gbd2, sbd
+
     # roofline of the dominant kernel, the reverse level kernel: one launch
     # per level, 2n launches per sweep; algorithmic FLOP of the sweep per
     # configuration = 4 (E + C) (the adjoint of every extension and close
@@ -830,6 +853,7 @@ def main():
         "adjoint_batched_over_plain": (nconf / (acc["adj"] / args.steps * 1e-3)) / adj_plain_rate,
         "adjoint_plain_check": {"configs": nadj, "S_equals_batched_bitwise": adj_plain_S_equal,
                                 "max_grad_dev_rel_to_max": adj_plain_grad_dev},
+        "deterministic_gradients": deterministic,
         "vs_oracle_refs": _refs_stats(WORKLOAD, S_host) if nconf == 2048 else None,
         "roofline": {"bound": "alu", "kernel": rev_kernel, "reverse_variant": rev_variant,
                      "note": "bound = the method's: FP64 ALU on algorithmic FLOP; the kernel itself streams every "

@@ -130,8 +130,11 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
 cos_status cos_set_workspace_limit(int64_t bytes);
 cos_status cos_batch_destroy(cos_batch_t b);
 
-/* Forward sum for every configuration of the batch, asynchronous on `stream`
- * (a hipStream_t, NULL = default stream).  Configurations are packed 64 to a
+/* Forward sum for every configuration of the batch (the connected sum of
+ * Results, "Theoretical Constructions", computed by the dynamic programme of
+ * Methods, Alg. 2/3: extensions, closes with the per-cycle weight, heads
+ * opened on the lowest once-visited vertex, SB-CoS shift heads), asynchronous
+ * on `stream` (a hipStream_t, NULL = default stream).  Configurations are packed 64 to a
  * group (one per lane) by order, largest order first; for each order there is
  * one launch per level of the state space (level = number of visited points,
  * 2n levels), each covering every group of that order.  No host
@@ -238,9 +241,12 @@ cos_status cos_chain_mu_shift(int32_t nconf, const int32_t *d_n, int32_t nmat,
                               const double *d_stub_bar, int32_t nstub, double U,
                               double *d_mu_bar, double *d_alpha_bar, void *stream);
 
-/* Plan counts for order n, per flavour (exact integers, host only):
- * states, extension transitions, closes, shift transitions, masks, rows
- * (a row = one (mask, head) pair). */
+/* Plan counts for order n, per flavour (exact integers, host only): the
+ * size of the dynamic programme's state space with visited sets merged for
+ * contact interactions (Results: the O(n^3 3^n) form with per-vertex counts
+ * 0, 1, 2): states, extension transitions, closes, shift transitions (the
+ * SB-CoS shift heads of Alg. 3), masks, rows (a row = one (mask, head) pair).
+ * COS_ERANGE for n outside [1, COS_NMAX]. */
 cos_status cos_plan_counts(int32_t n, int64_t *states, int64_t *extensions, int64_t *closes,
                            int64_t *shift_edges, int64_t *masks, int64_t *rows);
 
@@ -298,9 +304,10 @@ cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_wave
  * gradient once per workgroup; global_atomics = 0) or with global FP64
  * atomics straight into the packed gradient (LDS holds only G, so
  * workgroups are smaller and more fit a CU; global_atomics = 1, waves in
- * [1, 16]).  cos_batch_autotune tries both; these read and set the choice
- * (labelled batches keep the LDS accumulator).  COS_EINVAL for other values
- * or an order the batch does not have. */
+ * [1, 16]; with COS_F_SUBLATTICE at orders 7 and 8 this also keeps the whole
+ * 2n x 2n matrix in one workgroup instead of splitting its rows over two).
+ * cos_batch_autotune tries both; these read and set the choice.  COS_EINVAL
+ * for other values or an order the batch does not have. */
 cos_status cos_batch_reverse_variant(cos_batch_t b, int32_t n, int32_t *global_atomics, int32_t *waves);
 cos_status cos_batch_set_reverse_variant(cos_batch_t b, int32_t n, int32_t global_atomics, int32_t waves);
 

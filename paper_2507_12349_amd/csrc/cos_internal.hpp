@@ -147,8 +147,9 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // sublattice forward level (cos_sub.hip): `a.plan` is a sublattice plan, rows
 // hold 2n slots, GT holds 2n x 2n matrices; wpb <= 16
 hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s);
-// sublattice reverse level: adj_waves_per_block() wavefronts per workgroup
-hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipStream_t s);
+// sublattice reverse level: `wpb` wavefronts per workgroup (adj_waves_per_block()
+// with the LDS accumulator, at most 16 with global atomics)
+hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s);
 // nblocks = blocks of `a.mpb` masks; `wpb` wavefronts per workgroup (forward:
 // at most 8; reverse: at most 16, adj_waves_per_block() with the LDS accumulator)
 hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s);

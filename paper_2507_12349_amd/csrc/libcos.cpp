@@ -964,7 +964,7 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                 a.out_bar = d_out_bar;
                 a.Gbar_T = GbT;
                 a.sbar_T = sbT;
-                a.gacc = o.sub ? 0 : o.shape.adj_gacc;
+                a.gacc = o.shape.adj_gacc;
                 if (det) {
                     a.Gbar_T = Gp;
                     a.sbar_T = Sp;
@@ -972,7 +972,9 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                     LAUNCH_TRY(launch_level_det(a, cg, s));
                     continue;
                 }
-                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
+                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg,
+                                                           o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block(),
+                                                           s));
                 else LAUNCH_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg,
                                              o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block(), s));
             }
@@ -1084,12 +1086,11 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
         if (st) break;
         if (!d_out_bar || (b->flags & COS_F_DETERMINISTIC)) continue;   // the deterministic reverse has one shape
         // reverse: accumulator (LDS, or global atomics with 8 or 16 wavefronts
-        // per workgroup; the labelled kernels keep LDS) x masks per wavefront
+        // per workgroup) x masks per wavefront
         // (the forward part is the same for every candidate)
         tbest = 1e30f;
         static const int kAdjVariants[][2] = {{0, 16}, {1, 8}, {1, 16}};   // {global atomics, wavefronts}
         for (const auto &var : kAdjVariants) {
-            if (o.sub && var[0]) continue;
             for (int cap : kAdjCaps) {
                 o.shape.adj_gacc = var[0];
                 o.shape.adj_wpb = var[1];
@@ -1171,7 +1172,6 @@ cos_status cos_batch_set_reverse_variant(cos_batch_t b, int32_t n, int32_t globa
                     adj_waves_per_block());
     for (OrderGroup &o : b->orders)
         if (o.n == n) {
-            if (o.sub && global_atomics) return fail(COS_EINVAL, "labelled batches keep the LDS accumulator");
             o.shape.adj_gacc = global_atomics;
             o.shape.adj_wpb = waves;
             return COS_OK;

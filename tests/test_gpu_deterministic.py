@@ -15,12 +15,14 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(np.float64).eps
 
 
-def _adjoint(B, torch, G, st, n, nflav, variant, det, w=-1.0, shape=None, variant_rev=None, limit=0, mask=False):
+def _adjoint(B, torch, G, st, n, nflav, variant, det, w=-1.0, shape=None, variant_rev=None, limit=0, mask=False,
+             sub=False):
     nmat = nflav if variant else 1
-    nconf = G.numel() // (nmat * n * n)
+    side = 2 * n if sub else n
+    nconf = G.numel() // (nmat * side * side)
     B.set_workspace_limit(limit)
     b = B.Batch(np.full(nconf, n, dtype=np.int32), nflav, variant, stubs=st is not None, deterministic=det,
-                mask_only=mask)
+                mask_only=mask, sublattice=sub)
     B.set_workspace_limit(0)
     if shape:
         b.set_launch_shape(n, *shape)
@@ -100,3 +102,21 @@ def test_global_atomics_variant():
             assert np.all(np.abs(g0 - g1) <= 2 * 8 * n * (n + 2) * EPS * np.abs(ga) + 1e-300)
             if stubs:
                 assert np.all(np.abs(s0 - s1) <= 2 * 8 * n * (n + 2) * EPS * np.abs(sa) + 1e-300)
+
+
+def test_global_atomics_variant_labelled():
+    """The labelled reverse with global atomics keeps the whole 2n x 2n matrix
+    in one workgroup at orders 7 and 8 (no split of its rows): same sums, the
+    gradients within the FP64 bound of the split LDS-accumulator kernel."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("labelled reverse with global atomics vs the LDS accumulator, n=6, 7, 8, two flavours")
+    for n, nconf in ((6, 100), (7, 100), (8, 80)):
+        rng = np.random.default_rng(1100 + n)
+        G = torch.as_tensor(rng.normal(size=nconf * 2 * (2 * n) ** 2) * 0.25, device="cuda:0")
+        S0, g0, _ = _adjoint(B, torch, G, None, n, 2, 1, False, sub=True)
+        _, ga, _ = _adjoint(B, torch, G.abs(), None, n, 2, 1, False, w=1.0, sub=True)
+        for waves in (8, 16):
+            S1, g1, _ = _adjoint(B, torch, G, None, n, 2, 1, False, variant_rev=(1, waves), sub=True)
+            assert np.array_equal(S0, S1)
+            assert np.all(np.abs(g0 - g1) <= 2 * 8 * n * (n + 2) * EPS * np.abs(ga) + 1e-300)
