@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64 = 78.6e12           # MI355X FP64 vector peak, FLOP/s
 PEAK_HBM = 8.0e12             # MI355X HBM3E, bytes/s
-REV_KERNEL = "level_adj_kernel<%d, false, %s>"   # order, mask-only, global atomics
+REV_KERNEL = "level_adj_kernel<%d, false>"
 WORKLOAD = "adjoint"
 
 
@@ -144,8 +144,7 @@ def honeycomb_forward(B, torch, reps):
     grad = {"configs_per_s": n.size / (a0.elapsed_time(a1) / reps * 1e-3),
             "ms_per_step": a0.elapsed_time(a1) / reps,
             "phases_ms": {k: v / reps for k, v in aph.items()},
-            "kernel": "sub_adj_kernel<8, false, %s>" % ("true" if ba.reverse_variant(nn)["global_atomics"] else "false"),
-            "launch_shape": ba.launch_shape(nn), "reverse_variant": ba.reverse_variant(nn),
+            "kernel": "sub_adj_kernel<8, false>", "launch_shape": ba.launch_shape(nn),
             "S_equals_forward": bool(torch.equal(Sg, S))}
     ba.close()
     mask_only = {"forward_levels_ms": m0.elapsed_time(m1) / reps,
@@ -440,8 +439,7 @@ def workload_legs(B, torch, reps, cpu_threads=0, only=None):
             torch.cuda.synchronize()
             ams = a0.elapsed_time(a1) / reps
             leg.update({"fwd_adjoint_configs_per_s": nconf / (ams * 1e-3), "fwd_adjoint_ms": ams,
-                        "adjoint_S_equals_forward": bool(torch.equal(Sa, S)),
-                        "reverse_variant": b.reverse_variant(int(d.n[0]))})
+                        "adjoint_S_equals_forward": bool(torch.equal(Sa, S))})
             del Gb, sb, Sa
         if name in ("plain_single", "plain_batch"):
             # the plain form: one call per configuration (2n level launches, one of 64 lanes busy)
@@ -787,8 +785,7 @@ def main():
     launch_ms = rev_ms / nlaunch                       # average launch
     flop_launch = flop_rev * nconf / nlaunch
     achieved = flop_launch / (launch_ms * 1e-3)
-    rev_variant = batch.reverse_variant(n)
-    rev_kernel = REV_KERNEL % (n, "true" if rev_variant["global_atomics"] else "false")
+    rev_kernel = REV_KERNEL % n
     traffic = _traffic(rev_kernel)
     hbm = None
     if traffic is not None:
@@ -855,7 +852,7 @@ def main():
                                 "max_grad_dev_rel_to_max": adj_plain_grad_dev},
         "deterministic_gradients": deterministic,
         "vs_oracle_refs": _refs_stats(WORKLOAD, S_host) if nconf == 2048 else None,
-        "roofline": {"bound": "alu", "kernel": rev_kernel, "reverse_variant": rev_variant,
+        "roofline": {"bound": "alu", "kernel": rev_kernel,
                      "note": "bound = the method's: FP64 ALU on algorithmic FLOP; the kernel itself streams every "
                              "DP state through HBM (see hbm: AI ~1 FLOP/B, below the 9.8 FLOP/B ridge), which caps "
                              "frac near AI x 8 TB/s / 78.6 TFLOP/s",

@@ -299,18 +299,6 @@ cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves,
 cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_waves, int32_t fwd_masks,
                                       int32_t adj_masks);
 
-/* The reverse level kernel of order n accumulates dS/dG either in LDS (one
- * accumulator per workgroup of adj_waves 16 wavefronts, added to the packed
- * gradient once per workgroup; global_atomics = 0) or with global FP64
- * atomics straight into the packed gradient (LDS holds only G, so
- * workgroups are smaller and more fit a CU; global_atomics = 1, waves in
- * [1, 16]; with COS_F_SUBLATTICE at orders 7 and 8 this also keeps the whole
- * 2n x 2n matrix in one workgroup instead of splitting its rows over two).
- * cos_batch_autotune tries both; these read and set the choice.  COS_EINVAL
- * for other values or an order the batch does not have. */
-cos_status cos_batch_reverse_variant(cos_batch_t b, int32_t n, int32_t *global_atomics, int32_t *waves);
-cos_status cos_batch_set_reverse_variant(cos_batch_t b, int32_t n, int32_t global_atomics, int32_t waves);
-
 /* Phase timing, a measurement aid.  After cos_batch_timing_enable(b, 1),
  * every forward or adjoint call on b records HIP events on its own stream at
  * the boundaries of its phases (COS_PHASE_*).  cos_batch_timing_read waits

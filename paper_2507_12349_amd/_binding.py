@@ -27,7 +27,7 @@ EXPORTED = (
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
     "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape", "cos_set_workspace_limit",
     "cos_connected_sum_static", "cos_inject_failures", "cos_batch_set_adjoint_segments",
-    "cos_batch_adjoint_plan", "cos_batch_reverse_variant", "cos_batch_set_reverse_variant",
+    "cos_batch_adjoint_plan",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -71,8 +71,6 @@ def _load():
         "cos_connected_sum_static": ([i32, i32, i32, i32, i32, p, p, d, p, p], i32),
         "cos_inject_failures": ([i32, i32, i32], i32),
         "cos_batch_set_adjoint_segments": ([p, i32], i32),
-        "cos_batch_reverse_variant": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
-        "cos_batch_set_reverse_variant": ([p, i32, i32, i32], i32),
         "cos_batch_adjoint_plan": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), P64], i32),
         "cos_batch_launch_shape": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
     }
@@ -301,17 +299,6 @@ class Batch:
     def set_launch_shape(self, n: int, fwd_waves: int, fwd_masks: int, adj_masks: int):
         _check(lib.cos_batch_set_launch_shape(self._h, int(n), int(fwd_waves), int(fwd_masks), int(adj_masks)),
                "cos_batch_set_launch_shape")
-
-    def reverse_variant(self, n: int):
-        """{'global_atomics': 0 or 1, 'waves': wavefronts per workgroup} of the reverse kernel of order n."""
-        g, w = ctypes.c_int32(), ctypes.c_int32()
-        _check(lib.cos_batch_reverse_variant(self._h, int(n), ctypes.byref(g), ctypes.byref(w)),
-               "cos_batch_reverse_variant")
-        return {"global_atomics": g.value, "waves": w.value}
-
-    def set_reverse_variant(self, n: int, global_atomics: int, waves: int):
-        _check(lib.cos_batch_set_reverse_variant(self._h, int(n), int(global_atomics), int(waves)),
-               "cos_batch_set_reverse_variant")
 
     def set_adjoint_segments(self, segments: int):
         """0 automatic, 1 store every forward level, 2 two segments (lower

@@ -45,13 +45,6 @@ __device__ __forceinline__ void lane_st_nt(double *base, uint32_t lane8, double 
     asm volatile("" : "+s"(p));
     __builtin_nontemporal_store(x, (__attribute__((address_space(1))) double *)(p + lane8));
 }
-// atomic add to a lane's word of a 64-wide slot (device scope, no return value)
-__device__ __forceinline__ void lane_atomic_add(double *base, uint32_t lane8, double x) {
-    global_char *p = (global_char *)base;
-    asm volatile("" : "+s"(p));
-    __hip_atomic_fetch_add((__attribute__((address_space(1))) double *)(p + lane8), x, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
 __device__ __forceinline__ void lane_st(double *base, uint32_t lane8, double x) {
     global_char *p = (global_char *)base;
     asm volatile("" : "+s"(p));

@@ -131,7 +131,6 @@ struct LvlArgs {
     int32_t F_row0;
     int32_t level, group0, nfs, stubs, mpb;
     int32_t mask_only;        // SU(2) mask-only rules (two spin blocks as the two planes)
-    int32_t gacc;             // reverse: dS/dG terms by global atomics instead of an LDS accumulator
     int32_t det_groups;       // deterministic reverse: groups of the order (stride of the partial sums)
     double W;                 // factor of one closed cycle: w * nflav (uniform) or w
     double *out;              // forward, last level: S per configuration (may be null)
@@ -147,11 +146,10 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 // sublattice forward level (cos_sub.hip): `a.plan` is a sublattice plan, rows
 // hold 2n slots, GT holds 2n x 2n matrices; wpb <= 16
 hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s);
-// sublattice reverse level: `wpb` wavefronts per workgroup (adj_waves_per_block()
-// with the LDS accumulator, at most 16 with global atomics)
-hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s);
+// sublattice reverse level: adj_waves_per_block() wavefronts per workgroup
+hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipStream_t s);
 // nblocks = blocks of `a.mpb` masks; `wpb` wavefronts per workgroup (forward:
-// at most 8; reverse: at most 16, adj_waves_per_block() with the LDS accumulator)
+// at most 8; reverse: adj_waves_per_block())
 hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s);
 int adj_waves_per_block();
 // deterministic reverse sweep: every level's masks in kDetParts fixed parts;

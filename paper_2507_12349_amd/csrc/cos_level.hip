@@ -281,8 +281,8 @@ __global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
 // workgroup and flavour; only the (v, w) pairs a row can touch (v current,
 // w open or the head) are accumulated.
 // ---------------------------------------------------------------------------
-template <int N, bool MASK, bool GACC>
-__device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr, double *gbg,
+template <int N, bool MASK>
+__device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
                                         const double *__restrict__ F, const double *__restrict__ Bn,
                                         double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
                                         int64_t npl, int lam, int u, int r, bool start, double tb, double sgx,
@@ -336,23 +336,17 @@ __device__ __forceinline__ void adj_row(const MaskRec<N> &M, uint32_t gaddr, uin
         lane_st_nt(dst + v * 64, lane8, b);
 #pragma unroll
         for (int w = 0; w < N; ++w)
-            if (need & (1u << w)) {   // wave-uniform
-                if (GACC)
-                    lane_atomic_add(gbg + (v * N + w) * 64, lane8, f[v] * a[w]);
-                else
-                    __hip_atomic_fetch_add(Gb + (v * N + w) * 64, f[v] * a[w], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            if (need & (1u << w))   // wave-uniform
+                __hip_atomic_fetch_add(Gb + (v * N + w) * 64, f[v] * a[w], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
-// GACC: the dS/dG terms go straight to the packed gradient with global
-// atomics (LDS holds only G), instead of a workgroup accumulator in LDS
-template <int N, bool MASK, bool GACC>
+template <int N, bool MASK>
 __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
     double *Gs_all = lds;                     // [N * N][64]  G of the flavour
-    double *Gb_all = lds + N * N * 64;        // [N * N][64]  dS/dG of the flavour, this workgroup (not GACC)
+    double *Gb_all = lds + N * N * 64;        // [N * N][64]  dS/dG of the flavour, this workgroup
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
     const DevPlan &P = A.plan;
@@ -380,9 +374,8 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
         const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * N * N * 64;
         for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
             Gs_all[i] = gsrc[i];
-            if (!GACC) Gb_all[i] = 0.0;
+            Gb_all[i] = 0.0;
         }
-        double *gbg = A.Gbar_T + (int64_t)(g * nfs + lam) * N * N * 64;   // wave-uniform base
         if (threadIdx.x == 0) next_mask = blk0 + wpb;   // masks blk0 .. blk0 + wpb - 1 go to the waves in order
         __syncthreads();
         const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
@@ -407,8 +400,8 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             int u = 0, slot = 0;
             while (true) {
                 if (!(MASK && empty_plane(u, lam, twos)))
-                    adj_row<N, MASK, GACC>(M, gaddr, gbaddr, gbg, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot,
-                                           start, tb, sg * sc, sc, sacc);
+                    adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start, tb,
+                                     sg * sc, sc, sacc);
                 if (!hs) break;
                 u = __builtin_ctz(hs);
                 hs &= hs - 1u;
@@ -419,7 +412,6 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
             mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
         if (A.stubs && any) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
-        if (GACC) continue;
         __syncthreads();
         double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * N * N * 64;
         for (int i = threadIdx.x; i < N * N * 64; i += blockDim.x) {
@@ -651,32 +643,25 @@ hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups
     const int n = a.plan.n;
     if (!reverse && (wpb < 1 || wpb > 8)) return hipErrorInvalidValue;
     if (reverse) {
-        // the reverse takes `wpb` as its workgroup size (adj_waves_per_block() for the LDS accumulator)
-        const int wpa = wpb;
-        if (wpa < 1 || wpa > 16) return hipErrorInvalidValue;
-        const size_t shm = (a.gacc ? 1 : 2) * (size_t)n * n * 64 * sizeof(double);
+        const int wpa = adj_waves_per_block();
+        if (wpb != wpa) return hipErrorInvalidValue;
+        const size_t shm = 2 * (size_t)n * n * 64 * sizeof(double);
         const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups);
         switch (n) {
-#define COS_ADJ_LAUNCH(K, M, GA)                                                                  \
-    {                                                                                             \
-        hipError_t e = allow_lds((const void *)level_adj_kernel<K, M, GA>, shm);                  \
-        if (e != hipSuccess) return e;                                                            \
-        hipLaunchKernelGGL((level_adj_kernel<K, M, GA>), grid, dim3(64 * wpa), shm, s, a);        \
-    }
 #define COS_ADJ_CASE(K)                                                                           \
     case K: {                                                                                     \
-        if (a.mask_only) {                                                                        \
-            if (a.gacc) COS_ADJ_LAUNCH(K, true, true) else COS_ADJ_LAUNCH(K, true, false)         \
-        } else {                                                                                  \
-            if (a.gacc) COS_ADJ_LAUNCH(K, false, true) else COS_ADJ_LAUNCH(K, false, false)       \
-        }                                                                                         \
+        const void *fn = a.mask_only ? (const void *)level_adj_kernel<K, true>                    \
+                                     : (const void *)level_adj_kernel<K, false>;                  \
+        hipError_t e = allow_lds(fn, shm);                                                        \
+        if (e != hipSuccess) return e;                                                            \
+        if (a.mask_only) hipLaunchKernelGGL((level_adj_kernel<K, true>), grid, dim3(64 * wpa), shm, s, a);  \
+        else hipLaunchKernelGGL((level_adj_kernel<K, false>), grid, dim3(64 * wpa), shm, s, a);             \
         break;                                                                                    \
     }
             COS_ADJ_CASE(1) COS_ADJ_CASE(2) COS_ADJ_CASE(3) COS_ADJ_CASE(4)
             COS_ADJ_CASE(5) COS_ADJ_CASE(6) COS_ADJ_CASE(7) COS_ADJ_CASE(8)
             COS_ADJ_CASE(9) COS_ADJ_CASE(10) COS_ADJ_CASE(11) COS_ADJ_CASE(12)
 #undef COS_ADJ_CASE
-#undef COS_ADJ_LAUNCH
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

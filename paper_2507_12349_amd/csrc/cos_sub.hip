@@ -235,23 +235,20 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
 // child adjoints a, each reads its half of the states and writes its half
 // of B.
 // ---------------------------------------------------------------------------
-// GACC: the dS/dG terms go to the packed gradient with global atomics and LDS
-// holds only G, which then fits whole up to n = 8: no split, every child
-// adjoint read once
-template <int N, bool GACC>
+template <int N>
 struct SubAdjShape {
     static constexpr int D = 2 * N;
-    static constexpr bool SPLIT = !GACC && 2 * D * D * 64 * 8 > 160 * 1024;
+    static constexpr bool SPLIT = 2 * D * D * 64 * 8 > 160 * 1024;
     static constexpr int RI = SPLIT ? N : D;   // rows i owned by one workgroup
 };
 
-template <int N, bool MASK, bool GACC>
-__device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, uint32_t gbaddr, double *gbg,
+template <int N, bool MASK>
+__device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
                                             const double *__restrict__ F, const double *__restrict__ Bn,
                                             double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
                                             int64_t npl, int lam, int u, int su, int r, bool start, double tb,
                                             int i0) {
-    constexpr int D = 2 * N, RI = SubAdjShape<N, GACC>::RI;
+    constexpr int D = 2 * N, RI = SubAdjShape<N>::RI;
     const uint32_t ones = M.ones, twos = M.twos, subb = M.subb;
     const uint32_t cs = sub_current(N, u, su, ones, twos, subb) >> i0;   // owned rows, from bit 0
     if (!(cs & ((1u << RI) - 1u))) return;   // wave-uniform: nothing of this row is owned here
@@ -302,25 +299,21 @@ __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, 
         lane_st_nt(dst + k * 64, lane8, b);
 #pragma unroll
         for (int j = 0; j < D; ++j)
-            if ((need >> j) & 1u) {   // wave-uniform
-                if (GACC)
-                    lane_atomic_add(gbg + (k * D + j) * 64, lane8, f[k] * a[j]);
-                else
-                    __hip_atomic_fetch_add(Gb + (k * D + j) * 64, f[k] * a[j], __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            if ((need >> j) & 1u)   // wave-uniform
+                __hip_atomic_fetch_add(Gb + (k * D + j) * 64, f[k] * a[j], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
     }
 }
 
-template <int N, bool MASK, bool GACC>
+template <int N, bool MASK>
 __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
-    constexpr int D = 2 * N, RI = SubAdjShape<N, GACC>::RI;
+    constexpr int D = 2 * N, RI = SubAdjShape<N>::RI;
     extern __shared__ double lds[];
     double *Gs_all = lds;                      // [RI][D][64]  the owned rows of G
-    double *Gb_all = lds + RI * D * 64;        // [RI][D][64]  dS/dG of the owned rows, this workgroup (not GACC)
+    double *Gb_all = lds + RI * D * 64;        // [RI][D][64]  dS/dG of the owned rows, this workgroup
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
-    const int i0 = SubAdjShape<N, GACC>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
+    const int i0 = SubAdjShape<N>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
     // the workgroup's block of masks, claimed one at a time by its wavefronts
@@ -344,9 +337,8 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
         const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * D * D * 64 + (int64_t)i0 * D * 64;
         for (int i = threadIdx.x; i < RI * D * 64; i += blockDim.x) {
             Gs_all[i] = gsrc[i];
-            if (!GACC) Gb_all[i] = 0.0;
+            Gb_all[i] = 0.0;
         }
-        double *gbg = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64;   // wave-uniform base (GACC)
         if (threadIdx.x == 0) next_mask = blk0 + wpb;   // masks blk0 .. blk0 + wpb - 1 go to the waves in order
         __syncthreads();
         for (int mi = blk0 + wave; mi < blk1;) {
@@ -369,8 +361,8 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
             int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
             while (true) {
                 if (!(MASK && u == 0 && ((lam == 0) == full0)))
-                    sub_adj_row<N, MASK, GACC>(M, gaddr, gbaddr, gbg, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, su,
-                                               M.rb + slot, start, tb, i0);
+                    sub_adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, su, M.rb + slot,
+                                         start, tb, i0);
                 ++slot;
                 if (full0 && su == 0) {
                     su = 1;
@@ -385,7 +377,6 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
             if (lane == 0) nx = atomicAdd(&next_mask, 1);
             mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
-        if (GACC) continue;
         __syncthreads();
         double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64 + (int64_t)i0 * D * 64;
         for (int i = threadIdx.x; i < RI * D * 64; i += blockDim.x) {
@@ -428,32 +419,27 @@ hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb,
     return hipGetLastError();
 }
 
-hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s) {
+hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipStream_t s) {
     const int n = a.plan.n;
-    if (wpb < 1 || wpb > 16 || (!a.gacc && wpb != adj_waves_per_block())) return hipErrorInvalidValue;
+    const int wpa = adj_waves_per_block();
     const size_t side = 2 * (size_t)n, mat = side * side * 64 * sizeof(double);
-    const bool split = !a.gacc && 2 * mat > 160 * 1024;   // as SubAdjShape: two workgroups per block of masks
-    const size_t shm = (a.gacc || split) ? mat : 2 * mat;   // G (owned rows) and the LDS accumulator
-    const dim3 grid((unsigned)((nblocks + wpb - 1) / wpb), (unsigned)ngroups, split ? 2u : 1u);
+    const bool split = 2 * mat > 160 * 1024;   // as SubAdjShape: two workgroups per block of masks
+    const size_t shm = split ? mat : 2 * mat;   // owned rows of G and of the accumulator
+    const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups, split ? 2u : 1u);
     switch (n) {
-#define COS_SUBADJ_LAUNCH(K, M, GA)                                                                      \
-    {                                                                                                    \
-        hipError_t e = allow_sub_lds((const void *)sub_adj_kernel<K, M, GA>, shm);                       \
-        if (e != hipSuccess) return e;                                                                   \
-        hipLaunchKernelGGL((sub_adj_kernel<K, M, GA>), grid, dim3(64 * wpb), shm, s, a);                 \
-    }
 #define COS_SUBADJ_CASE(K)                                                                               \
-    case K:                                                                                              \
-        if (a.mask_only) {                                                                               \
-            if (a.gacc) COS_SUBADJ_LAUNCH(K, true, true) else COS_SUBADJ_LAUNCH(K, true, false)          \
-        } else {                                                                                         \
-            if (a.gacc) COS_SUBADJ_LAUNCH(K, false, true) else COS_SUBADJ_LAUNCH(K, false, false)        \
-        }                                                                                                \
-        break;
+    case K: {                                                                                            \
+        const void *fn = a.mask_only ? (const void *)sub_adj_kernel<K, true>                             \
+                                     : (const void *)sub_adj_kernel<K, false>;                           \
+        hipError_t e = allow_sub_lds(fn, shm);                                                           \
+        if (e != hipSuccess) return e;                                                                   \
+        if (a.mask_only) hipLaunchKernelGGL((sub_adj_kernel<K, true>), grid, dim3(64 * wpa), shm, s, a); \
+        else hipLaunchKernelGGL((sub_adj_kernel<K, false>), grid, dim3(64 * wpa), shm, s, a);            \
+        break;                                                                                           \
+    }
         COS_SUBADJ_CASE(1) COS_SUBADJ_CASE(2) COS_SUBADJ_CASE(3) COS_SUBADJ_CASE(4)
         COS_SUBADJ_CASE(5) COS_SUBADJ_CASE(6) COS_SUBADJ_CASE(7) COS_SUBADJ_CASE(8)
 #undef COS_SUBADJ_CASE
-#undef COS_SUBADJ_LAUNCH
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -391,8 +391,6 @@ struct LaunchShape {
     int fwd_wpb = 8;    // forward: wavefronts per workgroup (<= 8; sublattice: <= 16, default 16)
     int fwd_cap = 0;    // forward: most masks per wavefront (0: by flavour count)
     int adj_cap = 8;    // reverse: most masks per wavefront
-    int adj_wpb = 16;   // reverse: wavefronts per workgroup
-    int adj_gacc = 0;   // reverse: dS/dG by global atomics (LDS holds only G) instead of an LDS accumulator
 };
 
 // all configurations of one order inside a batch
@@ -964,7 +962,6 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                 a.out_bar = d_out_bar;
                 a.Gbar_T = GbT;
                 a.sbar_T = sbT;
-                a.gacc = o.shape.adj_gacc;
                 if (det) {
                     a.Gbar_T = Gp;
                     a.sbar_T = Sp;
@@ -972,11 +969,8 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                     LAUNCH_TRY(launch_level_det(a, cg, s));
                     continue;
                 }
-                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg,
-                                                           o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block(),
-                                                           s));
-                else LAUNCH_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg,
-                                             o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block(), s));
+                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
+                else LAUNCH_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
             }
             return COS_OK;
         };
@@ -1085,30 +1079,16 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
         o.shape = best;
         if (st) break;
         if (!d_out_bar || (b->flags & COS_F_DETERMINISTIC)) continue;   // the deterministic reverse has one shape
-        // reverse: accumulator (LDS, or global atomics with 8 or 16 wavefronts
-        // per workgroup) x masks per wavefront
-        // (the forward part is the same for every candidate)
+        // reverse: masks per wavefront (the forward part is the same for every candidate)
         tbest = 1e30f;
-        static const int kAdjVariants[][2] = {{0, 16}, {1, 8}, {1, 16}};   // {global atomics, wavefronts}
-        for (const auto &var : kAdjVariants) {
-            for (int cap : kAdjCaps) {
-                o.shape.adj_gacc = var[0];
-                o.shape.adj_wpb = var[1];
-                o.shape.adj_cap = cap;
-                float t;
-                st = time_best(s, 3, [&] {
-                    return adjoint_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar,
-                                         d_stub_bar, s);
-                }, &t);
-                if (st) break;
-                if (t < tbest) {
-                    tbest = t;
-                    best.adj_cap = cap;
-                    best.adj_gacc = var[0];
-                    best.adj_wpb = var[1];
-                }
-            }
+        for (int cap : kAdjCaps) {
+            o.shape.adj_cap = cap;
+            float t;
+            st = time_best(s, 3, [&] {
+                return adjoint_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out_bar, d_out, d_G_bar, d_stub_bar, s);
+            }, &t);
             if (st) break;
+            if (t < tbest) { tbest = t; best.adj_cap = cap; }
         }
         o.shape = best;
         if (st) break;
@@ -1148,32 +1128,6 @@ cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_wave
             o.shape.fwd_wpb = fwd_waves;
             o.shape.fwd_cap = fwd_masks;
             o.shape.adj_cap = adj_masks;
-            return COS_OK;
-        }
-    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
-}
-
-cos_status cos_batch_reverse_variant(cos_batch_t b, int32_t n, int32_t *global_atomics, int32_t *waves) {
-    if (!b || !global_atomics || !waves) return fail(COS_EINVAL, "null argument");
-    for (const OrderGroup &o : b->orders)
-        if (o.n == n) {
-            *global_atomics = o.shape.adj_gacc;
-            *waves = o.shape.adj_gacc ? o.shape.adj_wpb : adj_waves_per_block();
-            return COS_OK;
-        }
-    return fail(COS_EINVAL, "the batch has no configuration of order %d", n);
-}
-
-cos_status cos_batch_set_reverse_variant(cos_batch_t b, int32_t n, int32_t global_atomics, int32_t waves) {
-    if (!b) return fail(COS_EINVAL, "batch handle is NULL");
-    if (global_atomics != 0 && global_atomics != 1) return fail(COS_EINVAL, "global_atomics must be 0 or 1");
-    if (global_atomics ? (waves < 1 || waves > 16) : waves != adj_waves_per_block())
-        return fail(COS_EINVAL, "waves must be in [1, 16] with global atomics, %d with the LDS accumulator",
-                    adj_waves_per_block());
-    for (OrderGroup &o : b->orders)
-        if (o.n == n) {
-            o.shape.adj_gacc = global_atomics;
-            o.shape.adj_wpb = waves;
             return COS_OK;
         }
     return fail(COS_EINVAL, "the batch has no configuration of order %d", n);

@@ -210,8 +210,6 @@ def test_autotune_keeps_results():
     for k, sh in shapes.items():
         assert sh["fwd_waves"] in (4, 8) and sh["fwd_masks"] in (1, 2, 4, 8, 16), sh
         assert sh["adj_masks"] in (2, 4, 6, 8, 12, 16, 24, 32), sh
-        assert b.reverse_variant(k) in ({"global_atomics": 0, "waves": 16}, {"global_atomics": 1, "waves": 8},
-                                        {"global_atomics": 1, "waves": 16}), b.reverse_variant(k)
     with pytest.raises(B.CosError):
         b.launch_shape(5)
     S2 = torch.full_like(S0, float("nan"))

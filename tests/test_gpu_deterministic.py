@@ -1,11 +1,7 @@
-"""Deterministic gradients (COS_F_DETERMINISTIC) and the reverse variant with
-global atomics.
-
-Deterministic mode: dS/dG and dS/dsigma bit for bit equal across runs,
-forward launch shapes, reverse variants and chunkings of the groups, and
-within the FP64 bound of the default reverse sweep and of the oracle.
-Global-atomics variant of the default reverse: within the FP64 bound of the
-LDS-accumulator variant."""
+"""Deterministic gradients (COS_F_DETERMINISTIC): dS/dG and dS/dsigma bit for
+bit equal across runs, forward launch shapes, chunkings of the groups and
+two-segment sweeps, and within the FP64 bound of the default reverse sweep
+and of the oracle."""
 import numpy as np
 import pytest
 
@@ -15,8 +11,7 @@ pytestmark = pytest.mark.gpu
 EPS = np.finfo(np.float64).eps
 
 
-def _adjoint(B, torch, G, st, n, nflav, variant, det, w=-1.0, shape=None, variant_rev=None, limit=0, mask=False,
-             sub=False):
+def _adjoint(B, torch, G, st, n, nflav, variant, det, w=-1.0, shape=None, limit=0, mask=False, sub=False):
     nmat = nflav if variant else 1
     side = 2 * n if sub else n
     nconf = G.numel() // (nmat * side * side)
@@ -26,8 +21,6 @@ def _adjoint(B, torch, G, st, n, nflav, variant, det, w=-1.0, shape=None, varian
     B.set_workspace_limit(0)
     if shape:
         b.set_launch_shape(n, *shape)
-    if variant_rev:
-        b.set_reverse_variant(n, *variant_rev)
     out = torch.empty(nconf, dtype=torch.float64, device=G.device)
     Gb = torch.empty_like(G)
     sb = None if st is None else torch.empty_like(st)
@@ -84,39 +77,3 @@ def test_deterministic_gradients(oracle_mod, n, nflav, variant, stubs, mask, nco
             _, gref, _ = oracle_mod.dp_adjoint(Ga, nflav, variant, sc, -1.0)
             gd = g0[c * nmat * n * n:(c + 1) * nmat * n * n].reshape(Ga.shape)
             assert np.allclose(gd, ob[c] * gref, rtol=0, atol=1e-10 * np.abs(ob[c] * gref).max())
-
-
-def test_global_atomics_variant():
-    import torch
-    from paper_2507_12349_amd import _binding as B
-    announce("reverse variant with global atomics vs the LDS accumulator, n=10 and n=12")
-    for n, nconf, stubs in ((10, 200, True), (12, 70, False)):
-        rng = np.random.default_rng(1000 + n)
-        G = torch.as_tensor(rng.normal(size=nconf * n * n) * 0.3, device="cuda:0")
-        st = torch.as_tensor(rng.normal(size=(nconf, 1)) * 0.2, device="cuda:0") if stubs else None
-        S0, g0, s0 = _adjoint(B, torch, G, st, n, 4, 0, False)
-        for waves in (8, 16):
-            S1, g1, s1 = _adjoint(B, torch, G, st, n, 4, 0, False, variant_rev=(1, waves))
-            _, ga, sa = _adjoint(B, torch, G.abs(), None if st is None else -st.abs(), n, 4, 0, False, w=1.0)
-            assert np.array_equal(S0, S1)
-            assert np.all(np.abs(g0 - g1) <= 2 * 8 * n * (n + 2) * EPS * np.abs(ga) + 1e-300)
-            if stubs:
-                assert np.all(np.abs(s0 - s1) <= 2 * 8 * n * (n + 2) * EPS * np.abs(sa) + 1e-300)
-
-
-def test_global_atomics_variant_labelled():
-    """The labelled reverse with global atomics keeps the whole 2n x 2n matrix
-    in one workgroup at orders 7 and 8 (no split of its rows): same sums, the
-    gradients within the FP64 bound of the split LDS-accumulator kernel."""
-    import torch
-    from paper_2507_12349_amd import _binding as B
-    announce("labelled reverse with global atomics vs the LDS accumulator, n=6, 7, 8, two flavours")
-    for n, nconf in ((6, 100), (7, 100), (8, 80)):
-        rng = np.random.default_rng(1100 + n)
-        G = torch.as_tensor(rng.normal(size=nconf * 2 * (2 * n) ** 2) * 0.25, device="cuda:0")
-        S0, g0, _ = _adjoint(B, torch, G, None, n, 2, 1, False, sub=True)
-        _, ga, _ = _adjoint(B, torch, G.abs(), None, n, 2, 1, False, w=1.0, sub=True)
-        for waves in (8, 16):
-            S1, g1, _ = _adjoint(B, torch, G, None, n, 2, 1, False, variant_rev=(1, waves), sub=True)
-            assert np.array_equal(S0, S1)
-            assert np.all(np.abs(g0 - g1) <= 2 * 8 * n * (n + 2) * EPS * np.abs(ga) + 1e-300)
