@@ -369,9 +369,24 @@ cos_status cos_cdet_workspace(int32_t n, int32_t nconf, int32_t precision, uint6
 cos_status cos_cdet_su2(int32_t nconf, int32_t n, const double *d_A, int32_t precision, double eps,
                         void *d_work, uint64_t work_bytes, double *d_out, void *stream);
 
+/* Integer counting mode: the number of connected diagrams of order n when
+ * every propagator is 1 and every closed cycle carries the integer weight
+ * cycle_weight (x = w * N for the uniform SU(N) variant; x = +1 counts the
+ * diagrams, x = -N gives the sum with unit propagators and fermion loops),
+ * computed by the same dynamic programme in unsigned 64-bit integers on the
+ * device: *count is the exact count modulo 2^64, read as a signed number (so
+ * exact while |count| < 2^63: for x = +1 up to n = 10).  Synchronous, default
+ * stream.  The full sum over all diagrams is x (x + 1) ... (x + 2n - 1), and
+ * the connected counts follow from it by the exponential formula (Methods,
+ * connected-part recursion). */
+cos_status cos_connected_count(int32_t n, int64_t cycle_weight, int64_t *count);
+
 /* Testing aid for the error paths (no effect unless called): of the device
- * allocations (kind 0) or kernel launches (kind 1) the library makes from
- * now on, the next `skip` proceed and the `count` after them fail -- an
+ * allocations (kind 0) or kernel launches (kind 1) that the batch calls
+ * (cos_batch_create, the batched forward, reverse and autotuning calls,
+ * cos_connected_sum, cos_connected_sum_static) and the propagator, chain-rule,
+ * sampling and CDet calls make from now on, the next `skip` proceed and the
+ * `count` after them fail -- an
  * allocation as if the device were out of memory (the calls then return
  * COS_ENOMEM, or retry the level workspaces with smaller chunks, see
  * cos_set_workspace_limit), a launch is skipped and its call returns

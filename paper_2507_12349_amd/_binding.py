@@ -27,7 +27,7 @@ EXPORTED = (
     "cos_plan_counts_sublattice", "cos_build_g0_honeycomb", "cos_mc_sample", "cos_accumulate_moments", "cos_pade",
     "cos_cdet_workspace", "cos_cdet_su2", "cos_plan_counts_mask_only", "cos_batch_set_launch_shape", "cos_set_workspace_limit",
     "cos_connected_sum_static", "cos_inject_failures", "cos_batch_set_adjoint_segments",
-    "cos_batch_adjoint_plan",
+    "cos_batch_adjoint_plan", "cos_connected_count",
 )
 PHASES = ("pack", "forward", "reverse", "unpack")
 
@@ -70,6 +70,7 @@ def _load():
         "cos_batch_set_launch_shape": ([p, i32, i32, i32, i32], i32),
         "cos_connected_sum_static": ([i32, i32, i32, i32, i32, p, p, d, p, p], i32),
         "cos_inject_failures": ([i32, i32, i32], i32),
+        "cos_connected_count": ([i32, i64, P64], i32),
         "cos_batch_set_adjoint_segments": ([p, i32], i32),
         "cos_batch_adjoint_plan": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), P64], i32),
         "cos_batch_launch_shape": ([p, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)], i32),
@@ -150,6 +151,14 @@ def set_workspace_limit(nbytes: int):
     """Bound each level workspace of batches planned from now on (0: a share
     of the device memory free when the workspace is made)."""
     _check(lib.cos_set_workspace_limit(int(nbytes)), "cos_set_workspace_limit")
+
+
+def connected_count(n: int, x: int) -> int:
+    """Connected diagrams of order n with unit propagators and integer weight x
+    per cycle, counted on the device modulo 2^64 (returned as a signed int)."""
+    c = ctypes.c_int64()
+    _check(lib.cos_connected_count(int(n), int(x), ctypes.byref(c)), "cos_connected_count")
+    return c.value
 
 
 def inject_failures(kind: int, skip: int, count: int):

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 OUT = os.path.join(PKG, "libcos.so")
-SOURCES = ["cos_level.hip", "cos_sub.hip", "cos_kernels.hip", "cos_mc.hip", "cos_cdet.hip", "cos_static.hip", "libcos.cpp"]
+SOURCES = ["cos_level.hip", "cos_sub.hip", "cos_kernels.hip", "cos_mc.hip", "cos_cdet.hip", "cos_static.hip", "cos_count.hip", "libcos.cpp"]
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 FLAGS = [

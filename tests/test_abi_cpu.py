@@ -125,6 +125,11 @@ def test_argument_validation_without_device(B):
     assert st(4, 4, 2, 1, 0, None, None, -1.0, G.ctypes.data, None) == -1
     assert "orders 1..8" in (st(4, 9, 2, 0, 0, G.ctypes.data, None, -1.0, G.ctypes.data, None),
                              lib.cos_last_error().decode())[1]
+    # integer counting mode
+    c64 = ctypes.c_int64()
+    assert lib.cos_connected_count(0, 1, ctypes.byref(c64)) == -2
+    assert lib.cos_connected_count(13, 1, ctypes.byref(c64)) == -2
+    assert lib.cos_connected_count(4, 1, None) == -1
     # failure injection: kinds 0 (device allocation) and 1 (kernel launch) only
     assert lib.cos_inject_failures(2, 0, 1) == -1
     assert lib.cos_inject_failures(0, -1, 1) == -1

@@ -1,0 +1,31 @@
+"""Integer counting mode (cos_connected_count): the device DP with unit
+propagators and an integer weight per closed cycle, in unsigned 64-bit
+arithmetic, against the exact counts of the exponential formula
+(tests/golden/connected_counts.json, written from oracle.counts), n = 1..12,
+for the weights the golden file holds; equal modulo 2^64 (exact while the
+count fits in 63 bits, e.g. every n <= 10 for x = +1)."""
+import json
+import os
+
+import pytest
+
+from gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "connected_counts.json")
+
+
+def _signed64(v):
+    v %= 1 << 64
+    return v - (1 << 64) if v >= 1 << 63 else v
+
+
+def test_counts_match_exponential_formula():
+    from paper_2507_12349_amd import _binding as B
+    seqs = json.load(open(GOLDEN))["sequences"]
+    for x, seq in seqs.items():
+        announce("integer counts, weight %s per cycle, n = 1..12" % x)
+        for n, ref in enumerate(seq, start=1):
+            assert B.connected_count(n, int(x)) == _signed64(int(ref)), (x, n)
+    # the survey's value for x = +1, n = 10 (beyond FP64's exact range)
+    assert B.connected_count(10, 1) == 2281153623146496000
