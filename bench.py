@@ -548,7 +548,7 @@ def main():
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the other workloads (plain single, plain batch, symmetry broken, uneven)")
     ap.add_argument("--cpu-sample", type=int, default=1536)
-    ap.add_argument("--leg", choices=("plain_single", "plain_batch", "sym_broken", "uneven"),
+    ap.add_argument("--leg", choices=("plain_single", "plain_batch", "sym_broken", "uneven", "honeycomb"),
                     help="run only this workload's leg (for profiling; with --counters after the calibration copy)")
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
@@ -572,8 +572,12 @@ def main():
             torch.empty_like(src).copy_(src)
             torch.cuda.synchronize()
             del src
-        legs = workload_legs(B, torch, 1 if args.counters else max(3, args.steps // 2), 0, only=args.leg)
-        print(json.dumps({"leg": args.leg, "result": legs[args.leg]}), flush=True)
+        reps = 1 if args.counters else max(3, args.steps // 2)
+        if args.leg == "honeycomb":
+            res = honeycomb_forward(B, torch, reps)
+        else:
+            res = workload_legs(B, torch, reps, 0, only=args.leg)[args.leg]
+        print(json.dumps({"leg": args.leg, "result": res}), flush=True)
         return
 
     d = draw(WORKLOAD, nconf=args.nconf or None)

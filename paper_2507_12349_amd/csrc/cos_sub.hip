@@ -59,13 +59,15 @@ __device__ __forceinline__ int sub_child_base(const SubRec<N> &M, int i) {
 }
 
 template <int N, bool MASK>
-__device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, const double *__restrict__ cur,
-                                            double *__restrict__ nxt, uint32_t lane8, int64_t cpl, int64_t npl,
-                                            int lam, int u, int su, int r, bool start, double &cp, double &dext) {
+__device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, const double *__restrict__ curL,
+                                            double *__restrict__ nxtL, uint32_t lane8, int u, int su, int r,
+                                            bool start, double &cp, double &dext) {
     constexpr int D = 2 * N;
     const uint32_t ones = M.ones, twos = M.twos, subb = M.subb;
     const uint32_t cs = sub_current(N, u, su, ones, twos, subb);
-    const double *__restrict__ src = cur + lam * cpl + (int64_t)r * D * 64;
+    // curL, nxtL: this flavour's planes; row offsets in 32-bit (a level's rows
+    // times (2n)^2 x 64 stay far below 2^31)
+    const double *__restrict__ src = curL + r * D * 64;
     asm volatile("" : "+v"(gaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
     double f[D];
@@ -93,7 +95,7 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
             if (!ext) continue;
             if (!(ones & bit)) {
                 const int crow = M.crb[j] + sub_head_slot(u, su, twos);
-                lane_st_nt(nxt + lam * npl + (int64_t)crow * D * 64 + j * 64, lane8, MASK ? a : 2.0 * a);
+                lane_st_nt(nxtL + (crow * D + j) * 64, lane8, MASK ? a : 2.0 * a);
                 continue;
             }
             const double val = a;
@@ -104,19 +106,19 @@ __device__ __forceinline__ void sub_fwd_row(const SubRec<N> &M, uint32_t gaddr, 
                 continue;
             }
             const int crow = (s ? M.crb[2 * w + 1] : M.crb[2 * w]) + sub_head_slot(u, su, twos | bit);
-            lane_st_nt(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * w + s) * 64, lane8, val);
+            lane_st_nt(nxtL + (crow * D + 2 * w + s) * 64, lane8, val);
         }
     }
 }
 
 template <int N>
-__device__ __forceinline__ void sub_fwd_close(const SubRec<N> &M, double *__restrict__ nxt, uint32_t lane8,
-                                              int64_t npl, int lam, double t, double dext) {
+__device__ __forceinline__ void sub_fwd_close(const SubRec<N> &M, double *__restrict__ nxtL, uint32_t lane8,
+                                              double t, double dext) {
     constexpr int D = 2 * N;
     const int h = __builtin_ctz(M.ones);
     const int sh = (M.subb >> h) & 1u;
     const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, M.twos | (1u << h));
-    lane_st(nxt + lam * npl + (int64_t)crow * D * 64 + (2 * h + sh) * 64, lane8, t + (h == 0 ? dext : 0.0));
+    lane_st(nxtL + (crow * D + 2 * h + sh) * 64, lane8, t + (h == 0 ? dext : 0.0));
 }
 
 template <int N, bool MULTI, bool MASK>
@@ -149,41 +151,44 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
         const double *__restrict__ gsrc = A.GT + (int64_t)(g * nfs + lam) * D * D * 64;
         for (int i = threadIdx.x; i < D * D * 64; i += blockDim.x) Gs_all[i] = gsrc[i];
         __syncthreads();
+        const double *__restrict__ curL = cur + lam * cpl;
+        double *__restrict__ nxtL = nxt + lam * npl;
         const int mend = MULTI ? min(mb1, mb0 + K) : mb1;
-#pragma unroll
-        for (int k = 0; k < (MULTI ? K : 1); ++k) {
-            for (int mi = mb0 + k; mi < mend; mi += (MULTI ? K : 1)) {
-                const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
-                const uint32_t ones = M.ones, twos = M.twos;
-                const bool full0 = twos & 1u;            // vertex 0 visited twice: rows come in label pairs
-                uint32_t hs = full0 ? (twos & ~1u) : 0u;  // heads >= 1, ascending
-                int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
-                double cp = 0.0, dext = 0.0;
-                while (true) {
-                    // mask-only: rows of head vertex 0 use one plane (plane 0 while m_0 is once-visited)
-                    if (!(MASK && u == 0 && ((lam == 0) == full0)))
-                        sub_fwd_row<N, MASK>(M, gaddr, cur, nxt, lane8, cpl, npl, lam, u, su, M.rb + slot, start, cp,
-                                             dext);
-                    ++slot;
-                    if (full0 && su == 0) {
-                        su = 1;
-                        continue;
-                    }
-                    if (!hs) break;
-                    u = __builtin_ctz(hs);
-                    hs &= hs - 1u;
-                    su = 0;
+        // one copy of the mask body (the close sums of MULTI are picked by a
+        // select chain on the wave-uniform k, so that they stay in registers
+        // without unrolling the body K times)
+        for (int mi = mb0; mi < mend; ++mi) {
+            const int k = mi - mb0;
+            const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
+            const uint32_t ones = M.ones, twos = M.twos;
+            const bool full0 = twos & 1u;            // vertex 0 visited twice: rows come in label pairs
+            uint32_t hs = full0 ? (twos & ~1u) : 0u;  // heads >= 1, ascending
+            int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
+            double cp = 0.0, dext = 0.0;
+            while (true) {
+                // mask-only: rows of head vertex 0 use one plane (plane 0 while m_0 is once-visited)
+                if (!(MASK && u == 0 && ((lam == 0) == full0)))
+                    sub_fwd_row<N, MASK>(M, gaddr, curL, nxtL, lane8, u, su, M.rb + slot, start, cp, dext);
+                ++slot;
+                if (full0 && su == 0) {
+                    su = 1;
+                    continue;
                 }
-                if (MULTI) {
-                    cpk[k] += cp;
-                    if (!MASK && !last && (ones & 1u)) sub_fwd_close<N>(M, nxt, lane8, npl, lam, 0.0, dext);
-                } else {
-                    const double t = A.W * cp;
-                    if (last) {
-                        if (cfg >= 0 && A.out) A.out[cfg] = t;
-                    } else if (ones) {
-                        sub_fwd_close<N>(M, nxt, lane8, npl, 0, t, dext);
-                    }
+                if (!hs) break;
+                u = __builtin_ctz(hs);
+                hs &= hs - 1u;
+                su = 0;
+            }
+            if (MULTI) {
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) cpk[kk] = (kk == k) ? cpk[kk] + cp : cpk[kk];
+                if (!MASK && !last && (ones & 1u)) sub_fwd_close<N>(M, nxtL, lane8, 0.0, dext);
+            } else {
+                const double t = A.W * cp;
+                if (last) {
+                    if (cfg >= 0 && A.out) A.out[cfg] = t;
+                } else if (ones) {
+                    sub_fwd_close<N>(M, nxt, lane8, t, dext);
                 }
             }
         }
@@ -231,9 +236,12 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
 // adding the accumulator to the packed gradient once per flavour.  Up to
 // n = 6 one workgroup owns every row i (2 x 72 KB at n = 6); at n = 7, 8 the
 // two matrices would not fit (2 x 128 KB at n = 8), so two workgroups share
-// a block of masks, each owning half of the rows i (grid z): both read the
-// child adjoints a, each reads its half of the states and writes its half
-// of B.
+// a block of masks, each owning half of the rows i: both read the child
+// adjoints a, each reads its half of the states and writes its half of B.
+// The two halves of a block are workgroups 8 apart in dispatch order, which
+// the dispatcher sends to the same XCD one after the other, so that the
+// second read of the child adjoints is served by that XCD's L2 rather than
+// by HBM.
 // ---------------------------------------------------------------------------
 template <int N>
 struct SubAdjShape {
@@ -244,16 +252,17 @@ struct SubAdjShape {
 
 template <int N, bool MASK>
 __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, uint32_t gbaddr,
-                                            const double *__restrict__ F, const double *__restrict__ Bn,
-                                            double *__restrict__ Bc, uint32_t lane8, int64_t fpl, int64_t cpl,
-                                            int64_t npl, int lam, int u, int su, int r, bool start, double tb,
-                                            int i0) {
+                                            const double *__restrict__ FL, const double *__restrict__ BnL,
+                                            double *__restrict__ BcL, uint32_t lane8, int u, int su, int r,
+                                            bool start, double tb, int i0) {
     constexpr int D = 2 * N, RI = SubAdjShape<N>::RI;
     const uint32_t ones = M.ones, twos = M.twos, subb = M.subb;
     const uint32_t cs = sub_current(N, u, su, ones, twos, subb) >> i0;   // owned rows, from bit 0
     if (!(cs & ((1u << RI) - 1u))) return;   // wave-uniform: nothing of this row is owned here
     const int k0 = __builtin_ctz(cs);
-    const double *__restrict__ src = F + lam * fpl + (int64_t)r * D * 64 + (int64_t)i0 * 64;
+    // FL, BnL, BcL: this flavour's planes; row offsets in 32-bit (a level's
+    // rows times (2n)^2 x 64 stay far below 2^31)
+    const double *__restrict__ src = FL + (r * D + i0) * 64;
     // straight-line loads with selects (unused ones re-read a needed slot)
     double f[RI], a[D];
 #pragma unroll
@@ -273,7 +282,7 @@ __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, 
             bool ext = !(twos & bit) && (!once || (int)((subb >> w) & 1u) == s);
             if (MASK && once && w == 0 && u == 0) ext = false;   // the head point itself
             const int crow = ext ? M.crb[j] + sub_head_slot(u, su, once ? (twos | bit) : twos) : 0;
-            const double bc = lane_ld(Bn + (ext ? lam * cpl + (int64_t)crow * D * 64 + j * 64 : 0), lane8);
+            const double bc = lane_ld(BnL + (ext ? (crow * D + j) * 64 : 0), lane8);
             a[j] = ext ? ((!once && !MASK) ? 2.0 * bc : bc) : 0.0;
             if (ext) need |= 1u << j;
         }
@@ -286,16 +295,16 @@ __device__ __forceinline__ void sub_adj_row(const SubRec<N> &M, uint32_t gaddr, 
     asm volatile("" : "+v"(gbaddr));
     const lds_double *Gs = (const lds_double *)(uintptr_t)gaddr;
     lds_double *Gb = (lds_double *)(uintptr_t)gbaddr;
-    double *__restrict__ dst = Bc + lam * npl + (int64_t)r * D * 64 + (int64_t)i0 * 64;
+    double *__restrict__ dst = BcL + (r * D + i0) * 64;
 #pragma unroll
     for (int k = 0; k < RI; ++k) {
         if (!((cs >> k) & 1u)) continue;   // wave-uniform
+        // every output j, a[j] = 0 where nothing is needed: straight-line LDS
+        // reads that issue together and are waited for once, rather than one
+        // read-and-wait per needed output behind a branch
         double b = 0.0;
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            if (!((need >> j) & 1u)) continue;   // wave-uniform
-            b = __builtin_fma((double)Gs[(k * D + j) * 64], a[j], b);
-        }
+        for (int j = 0; j < D; ++j) b = __builtin_fma((double)Gs[(k * D + j) * 64], a[j], b);
         lane_st_nt(dst + k * 64, lane8, b);
 #pragma unroll
         for (int j = 0; j < D; ++j)
@@ -313,11 +322,15 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
     double *Gb_all = lds + RI * D * 64;        // [RI][D][64]  dS/dG of the owned rows, this workgroup
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
-    const int i0 = SubAdjShape<N>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
+    // split: workgroup x of the launch is half (x / 8) % 2 of block (x / 16) * 8 + x % 8
+    const int bx = (int)blockIdx.x;
+    const int blk = SubAdjShape<N>::SPLIT ? ((bx >> 4) << 3) + (bx & 7) : bx;
+    const int i0 = SubAdjShape<N>::SPLIT ? ((bx >> 3) & 1) * RI : 0;   // first owned row i
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
     // the workgroup's block of masks, claimed one at a time by its wavefronts
-    const int blk0 = blockIdx.x * wpb * A.mpb;
+    const int blk0 = blk * wpb * A.mpb;
+    if (blk0 >= L.w) return;   // padding workgroup of the split launch (the whole workgroup leaves)
     const int blk1 = min(blk0 + wpb * A.mpb, L.w);   // may hold fewer masks than waves: they still join the barriers
     __shared__ int next_mask;
     const int gl = blockIdx.y, g = A.group0 + gl;
@@ -341,6 +354,9 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
         }
         if (threadIdx.x == 0) next_mask = blk0 + wpb;   // masks blk0 .. blk0 + wpb - 1 go to the waves in order
         __syncthreads();
+        const double *__restrict__ FL = F + lam * fpl;
+        const double *__restrict__ BnL = Bn + lam * cpl;
+        double *__restrict__ BcL = Bc + lam * npl;
         for (int mi = blk0 + wave; mi < blk1;) {
             const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
             const uint32_t ones = M.ones, twos = M.twos;
@@ -361,8 +377,7 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
             int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
             while (true) {
                 if (!(MASK && u == 0 && ((lam == 0) == full0)))
-                    sub_adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, su, M.rb + slot,
-                                         start, tb, i0);
+                    sub_adj_row<N, MASK>(M, gaddr, gbaddr, FL, BnL, BcL, lane8, u, su, M.rb + slot, start, tb, i0);
                 ++slot;
                 if (full0 && su == 0) {
                     su = 1;
@@ -425,7 +440,10 @@ hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipS
     const size_t side = 2 * (size_t)n, mat = side * side * 64 * sizeof(double);
     const bool split = 2 * mat > 160 * 1024;   // as SubAdjShape: two workgroups per block of masks
     const size_t shm = split ? mat : 2 * mat;   // owned rows of G and of the accumulator
-    const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups, split ? 2u : 1u);
+    const unsigned nb = (unsigned)((nblocks + wpa - 1) / wpa);
+    // split: both halves of each block, paired 8 workgroups apart (a multiple of
+    // 16 workgroups per group, so that the pairing holds in every group)
+    const dim3 grid(split ? 2u * ((nb + 7u) & ~7u) : nb, (unsigned)ngroups);
     switch (n) {
 #define COS_SUBADJ_CASE(K)                                                                               \
     case K: {                                                                                            \
