@@ -236,12 +236,9 @@ __global__ void __launch_bounds__(1024) sub_fwd_kernel(const LvlArgs A) {
 // adding the accumulator to the packed gradient once per flavour.  Up to
 // n = 6 one workgroup owns every row i (2 x 72 KB at n = 6); at n = 7, 8 the
 // two matrices would not fit (2 x 128 KB at n = 8), so two workgroups share
-// a block of masks, each owning half of the rows i: both read the child
-// adjoints a, each reads its half of the states and writes its half of B.
-// The two halves of a block are workgroups 8 apart in dispatch order, which
-// the dispatcher sends to the same XCD one after the other, so that the
-// second read of the child adjoints is served by that XCD's L2 rather than
-// by HBM.
+// a block of masks, each owning half of the rows i (grid z): both read the
+// child adjoints a, each reads its half of the states and writes its half of
+// B.
 // ---------------------------------------------------------------------------
 template <int N>
 struct SubAdjShape {
@@ -322,15 +319,11 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
     double *Gb_all = lds + RI * D * 64;        // [RI][D][64]  dS/dG of the owned rows, this workgroup
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
     const int wpb = blockDim.x >> 6;
-    // split: workgroup x of the launch is half (x / 8) % 2 of block (x / 16) * 8 + x % 8
-    const int bx = (int)blockIdx.x;
-    const int blk = SubAdjShape<N>::SPLIT ? ((bx >> 4) << 3) + (bx & 7) : bx;
-    const int i0 = SubAdjShape<N>::SPLIT ? ((bx >> 3) & 1) * RI : 0;   // first owned row i
+    const int i0 = SubAdjShape<N>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
     // the workgroup's block of masks, claimed one at a time by its wavefronts
-    const int blk0 = blk * wpb * A.mpb;
-    if (blk0 >= L.w) return;   // padding workgroup of the split launch (the whole workgroup leaves)
+    const int blk0 = blockIdx.x * wpb * A.mpb;
     const int blk1 = min(blk0 + wpb * A.mpb, L.w);   // may hold fewer masks than waves: they still join the barriers
     __shared__ int next_mask;
     const int gl = blockIdx.y, g = A.group0 + gl;
@@ -440,10 +433,7 @@ hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipS
     const size_t side = 2 * (size_t)n, mat = side * side * 64 * sizeof(double);
     const bool split = 2 * mat > 160 * 1024;   // as SubAdjShape: two workgroups per block of masks
     const size_t shm = split ? mat : 2 * mat;   // owned rows of G and of the accumulator
-    const unsigned nb = (unsigned)((nblocks + wpa - 1) / wpa);
-    // split: both halves of each block, paired 8 workgroups apart (a multiple of
-    // 16 workgroups per group, so that the pairing holds in every group)
-    const dim3 grid(split ? 2u * ((nb + 7u) & ~7u) : nb, (unsigned)ngroups);
+    const dim3 grid((unsigned)((nblocks + wpa - 1) / wpa), (unsigned)ngroups, split ? 2u : 1u);
     switch (n) {
 #define COS_SUBADJ_CASE(K)                                                                               \
     case K: {                                                                                            \
