@@ -118,7 +118,10 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav,
 /* Upper bound, in bytes, on each of the two level workspaces of batches
  * planned from now on in this process (the forward's two level windows, made
  * at cos_batch_create; the reverse sweep's stored forward levels, made at the
- * first reverse call).  A batch whose groups of 64 configurations do not all
+ * first reverse call).  A batch of several orders may take up to half of the
+ * bound again for the windows of the orders its forward runs on a second
+ * stream (cos_connected_sum_batched), only if that fits, else it runs every
+ * order on the caller's stream.  A batch whose groups of 64 configurations do not all
  * fit runs them in chunks of as many groups as fit (at least one), one after
  * the other; results do not depend on the chunking (S bitwise).  0 (the
  * initial setting) bounds the windows by 45% of the device memory free at
@@ -137,8 +140,17 @@ cos_status cos_batch_destroy(cos_batch_t b);
  * on `stream` (a hipStream_t, NULL = default stream).  Configurations are packed 64 to a
  * group (one per lane) by order, largest order first; for each order there is
  * one launch per level of the state space (level = number of visited points,
- * 2n levels), each covering every group of that order.  No host
- * synchronisation, no allocation: capturable in a graph.
+ * 2n levels), each covering every group of that order.  With two or more
+ * orders, the orders after the largest (after the two largest when the
+ * others' windows would not fit) run on a second stream of the batch (made
+ * at cos_batch_create, default priority, with level windows of their own,
+ * up to half of the workspace bound on top of the forward's windows; see
+ * cos_set_workspace_limit), forked from `stream` at the call's start and
+ * joined back into it (event waits queued on the streams), so that their
+ * launches overlap the large orders' small levels; the sums are the same
+ * either way (bitwise).  No host
+ * synchronisation, no allocation: capturable in a graph (the fork and join
+ * are event waits).
  * d_Goff may be NULL when the configurations are stored back to back.
  * d_stub is required iff the batch was planned with COS_F_STUBS.
  * Writes d_out[c] = S_c. */

@@ -405,6 +405,7 @@ struct OrderGroup {
     int64_t sp_off = 0;                // deterministic reverse: offset into the shift partial sums
     LaunchShape shape;                 // launch shape of the level kernels (autotuned)
     bool sub = false;                  // sublattice-labelled states (2n slots per row)
+    bool side = false;                 // forward on the batch's side stream, in the side windows
     std::shared_ptr<HostPlan> hp;
     int slots() const { return sub ? 2 * n : n; }
 };
@@ -423,6 +424,16 @@ struct cos_batch_s {
     int32_t *d_lane = nullptr;
     double *d_win = nullptr;           // forward level windows
     int64_t win_doubles = 0;
+    // with two or more orders the batched forward runs the orders after the
+    // largest (or after the two largest, when the windows of the others would
+    // not fit) on a second stream (default priority), in level windows of
+    // their own, while the rest run on the caller's stream: the side orders'
+    // launches fill the chip while the large ones are in their small first
+    // and last levels
+    size_t side_first = 0;             // first order on the side stream (0: none)
+    double *d_win2 = nullptr;          // the side orders' level windows (each order in one chunk)
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // reverse sweep (allocated on first use)
     double *d_Fall = nullptr, *d_GbT = nullptr, *d_sbT = nullptr;
     double *d_Gpart = nullptr, *d_Spart = nullptr;   // deterministic reverse: per-part partial sums
@@ -650,6 +661,38 @@ cos_status cos_batch_create(int32_t nconf, const int32_t *n, int32_t nflav, int3
         if ((st = alloc_chunked(&b->d_win, chunks, ng, b->ws_cap, per_group, total, "level window"))) return st;
         for (size_t i = 0; i < chunks.size(); ++i) b->orders[i].chunk_fwd = chunks[i];
         b->win_doubles = total();
+        // side stream for the orders after the largest (else after the two
+        // largest) when their windows, each order whole, take at most half of
+        // the workspace bound; otherwise, or if any of it cannot be had, every
+        // order runs on the caller's stream
+        size_t first = 0;
+        int64_t w2 = 0;
+        for (size_t f = 1; f <= 2 && !first && f < b->orders.size(); ++f) {
+            int64_t w = 0;
+            for (size_t i = f; i < b->orders.size(); ++i) w = std::max(w, per_group(i) * b->orders[i].ngroups);
+            if (8 * w <= b->ws_cap / 2) first = f, w2 = w;
+        }
+        if (first) {
+            bool ok = dev_malloc((void **)&b->d_win2, sizeof(double) * w2) == hipSuccess;
+            ok = ok && hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) == hipSuccess;
+            if (ok) {
+                b->side_first = first;
+                for (size_t i = first; i < b->orders.size(); ++i) {
+                    b->orders[i].side = true;
+                    b->orders[i].chunk_fwd = b->orders[i].ngroups;
+                }
+            } else {
+                (void)hipGetLastError();
+                (void)hipFree(b->d_win2);
+                b->d_win2 = nullptr;
+                if (b->side) (void)hipStreamDestroy(b->side);
+                if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+                b->side = nullptr;
+                b->ev_fork = nullptr;
+            }
+        }
     }
     HIP_TRY(hipMemcpy(b->d_order, order.data(), sizeof(int32_t) * nconf, hipMemcpyHostToDevice));
     {
@@ -668,6 +711,10 @@ cos_status cos_batch_destroy(cos_batch_t b) {
     (void)hipFree(b->d_sigT);
     (void)hipFree(b->d_lane);
     (void)hipFree(b->d_win);
+    (void)hipFree(b->d_win2);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     (void)hipFree(b->d_Fall);
     (void)hipFree(b->d_GbT);
     (void)hipFree(b->d_sbT);
@@ -759,17 +806,20 @@ static int adj_masks(const LaunchShape &sh, int nm, int ng, int ncu) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(sh.adj_cap, (work + slots * rounds - 1) / (slots * rounds)));
 }
 
-// forward levels of one order, all groups, chunk by chunk (two level windows)
+// forward levels of one order, all groups, chunk by chunk (two level windows:
+// the side windows for a side order); `mark`: record the phase marks on s
 static cos_status forward_order(cos_batch_t b, const OrderGroup &o, const double *d_G, const int64_t *d_Goff,
-                                const double *d_stub, double cycle_weight, double *d_out, hipStream_t s) {
-    HIP_TRY(tmark(b, COS_PHASE_PACK, s));
+                                const double *d_stub, double cycle_weight, double *d_out, hipStream_t s,
+                                bool mark = true) {
+    if (mark) HIP_TRY(tmark(b, COS_PHASE_PACK, s));
     LAUNCH_TRY(launch_pack(pack_args(b, o, d_G, d_Goff, d_stub), s));
-    HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
+    if (mark) HIP_TRY(tmark(b, COS_PHASE_FORWARD, s));
     const int64_t rs = (int64_t)b->nfs * o.slots() * 64;
     const int64_t gstride = (int64_t)o.hp->max_rows * rs;
+    double *const base = o.side ? b->d_win2 : b->d_win;
     for (int c0 = 0; c0 < o.ngroups; c0 += o.chunk_fwd) {
         const int cg = std::min(o.chunk_fwd, o.ngroups - c0);
-        double *win0 = b->d_win, *win1 = b->d_win + gstride * cg;
+        double *win0 = base, *win1 = base + gstride * cg;
         for (int l = 1; l <= 2 * o.n; ++l) {
             LvlArgs a = level_args(b, o, cycle_weight);
             a.level = l;
@@ -796,8 +846,26 @@ cos_status cos_connected_sum_batched(cos_batch_t b, const double *d_G, const int
     if ((st = check_weight(b->flags, cycle_weight))) return st;
     if (!d_out) return fail(COS_EINVAL, "d_out is NULL");
     hipStream_t s = (hipStream_t)stream;
-    for (const OrderGroup &o : b->orders)
-        if ((st = forward_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out, s))) return st;
+    if (!b->side_first) {
+        for (const OrderGroup &o : b->orders)
+            if ((st = forward_order(b, o, d_G, d_Goff, d_stub, cycle_weight, d_out, s))) return st;
+        HIP_TRY(tmark(b, -1, s));
+        return COS_OK;
+    }
+    // fork: the side orders start after what s holds so far; join: s waits
+    // for them (also after a failure, so that no side work outlives the call's
+    // place on s); the phase marks stay on s
+    HIP_TRY(hipEventRecord(b->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(b->side, b->ev_fork, 0));
+    cos_status st_side = COS_OK, st_main = COS_OK;
+    for (size_t i = b->side_first; i < b->orders.size() && !st_side; ++i)
+        st_side = forward_order(b, b->orders[i], d_G, d_Goff, d_stub, cycle_weight, d_out, b->side, false);
+    for (size_t i = 0; i < b->side_first && !st_main; ++i)
+        st_main = forward_order(b, b->orders[i], d_G, d_Goff, d_stub, cycle_weight, d_out, s);
+    HIP_TRY(hipEventRecord(b->ev_join, b->side));
+    HIP_TRY(hipStreamWaitEvent(s, b->ev_join, 0));
+    if (st_side) return st_side;
+    if (st_main) return st_main;
     HIP_TRY(tmark(b, -1, s));
     return COS_OK;
 }

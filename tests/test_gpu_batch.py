@@ -93,6 +93,55 @@ def test_graph_replay_with_new_inputs():
     b.close()
 
 
+def test_graph_replay_forward_uneven_side_stream():
+    """An uneven batch of five orders runs the four after the largest on the
+    batch's side stream (a fork from the caller's stream and a join back).
+    Capture the batched forward in a graph, replay it three times with new
+    matrices (eager work and a synchronisation between replays), and compare
+    every replay with an eager call and with one batch per order, bitwise."""
+    import torch
+    from paper_2507_12349_amd import _binding as B
+    announce("graph capture / replay of an uneven forward with a side stream (5 orders)")
+    rng = np.random.default_rng(41)
+    orders = [10, 4, 8, 6, 10, 5, 8, 4, 6] * 8
+    nconf = len(orders)
+    flat, off, n = pack([rng.normal(size=(3, k, k)) * 0.5 for k in orders])
+    b = B.Batch(n, 3, 1, stubs=False)
+    G = _dev(flat).clone()
+    Goff = _dev(off)
+    out = torch.zeros(nconf, dtype=torch.float64, device="cuda:0")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.forward(G, Goff, None, -1.0, out, s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.forward(G, Goff, None, -1.0, out, s)
+    ref = torch.zeros_like(out)
+    for k in range(3):
+        mats = [rng.normal(size=(3, x, x)) * 0.5 for x in orders]
+        G.copy_(_dev(pack(mats)[0]))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.clone()
+        b.forward(G, Goff, None, -1.0, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref), k
+        whole = got.cpu().numpy()
+        for m in sorted(set(orders)):
+            sel = [i for i, x in enumerate(orders) if x == m]
+            f2, o2, n2 = pack([mats[i] for i in sel])
+            b2 = B.Batch(n2, 3, 1)
+            o = torch.full((len(sel),), float("nan"), dtype=torch.float64, device="cuda:0")
+            b2.forward(_dev(f2), _dev(o2), None, -1.0, o)
+            assert np.array_equal(o.cpu().numpy(), whole[sel]), (k, m)
+            b2.close()
+    b.close()
+
+
 def test_graph_replay_adjoint_uneven():
     """The adjoint of an uneven batch (orders 5, 7, 9; three flavours with
     shifts) captured once and replayed with new inputs: S equals an eager call
