@@ -95,3 +95,42 @@ def test_launch_failure():
     finally:
         B.inject_failures(1, 0, 0)
         b.close()
+
+
+@pytest.mark.parametrize("skip", [2, 40])
+def test_launch_failure_side_stream(skip):
+    """A batch of three orders runs the two smaller ones on its side stream.
+    A failed launch there (skip = 2: the side stream's pack and first level
+    proceed) or on the caller's stream (skip = 40: past the side orders'
+    launches) surfaces as COS_EDEVICE, the call still joins the side stream
+    back (the caller's stream drains), and the next call gives the sums of a
+    fresh batch."""
+    import torch
+    from gpu_util import pack
+    from paper_2507_12349_amd import _binding as B
+    announce("injected launch failure with a side stream (skip %d)" % skip)
+    rng = np.random.default_rng(79 + skip)
+    orders = [8, 6, 5] * 30
+    flat, off, n = pack([rng.normal(size=(2, k, k)) * 0.5 for k in orders])
+    G, Goff = torch.as_tensor(flat, device="cuda:0"), torch.as_tensor(off, device="cuda:0")
+    out = torch.empty(len(orders), dtype=torch.float64, device="cuda:0")
+    ref = torch.empty_like(out)
+    r = B.Batch(n, 2, B.FLAVOUR)
+    r.forward(G, Goff, None, -1.0, ref)
+    torch.cuda.synchronize()
+    r.close()
+    b = B.Batch(n, 2, B.FLAVOUR)
+    try:
+        B.inject_failures(1, skip, 1)
+        with pytest.raises(B.CosError) as e:
+            b.forward(G, Goff, None, -1.0, out)
+        assert e.value.status == -4 and "injected" in str(e.value)
+        B.inject_failures(1, 0, 0)
+        torch.cuda.synchronize()
+        out.fill_(float("nan"))
+        b.forward(G, Goff, None, -1.0, out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    finally:
+        B.inject_failures(1, 0, 0)
+        b.close()
