@@ -288,7 +288,7 @@ cos_status cos_batch_adjoint_plan(cos_batch_t b, int32_t n, int32_t *split_level
  * inputs for each candidate launch shape -- wavefronts per workgroup of the
  * forward kernel (4, 8; 8, 16 with COS_F_SUBLATTICE) and the most masks
  * (state-table tiles) per wavefront of the forward (1, 2, 4, 8, 16) and, when
- * d_out_bar is not NULL, of the reverse kernel (2, 4, 6, 8, 12, 16, 24, 32;
+ * d_out_bar is not NULL, of the reverse kernel (2, 4, 6, 8, 12, 16, 24, 32, 48, 64;
  * a reverse level is cut into as few rounds of one workgroup per CU as that
  * cap allows, its masks spread evenly) -- keeps the fastest per order and
  * uses it for every later call on b.  Arguments as cos_connected_sum_batched

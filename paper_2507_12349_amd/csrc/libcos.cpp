@@ -1130,7 +1130,7 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
     b->timing = false;
     static const int kWaves[] = {4, 8}, kSubWaves[] = {8, 16};
     static const int kCaps[] = {1, 2, 4, 8, 16};
-    static const int kAdjCaps[] = {2, 4, 6, 8, 12, 16, 24, 32};
+    static const int kAdjCaps[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
     for (OrderGroup &o : b->orders) {
         // forward: waves per workgroup x masks per wavefront
         LaunchShape best = o.shape;
