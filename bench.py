@@ -554,6 +554,9 @@ def main():
     ap.add_argument("--counters", action="store_true",
                     help="run one calibration copy (1 GiB), one batched forward and one adjoint, "
                          "then exit (for rocprofv3 --pmc passes)")
+    ap.add_argument("--shape", default=None,
+                    help="with --counters: launch shape FWD_WAVES,FWD_MASKS,ADJ_MASKS of the adjoint workload's "
+                         "calls (the autotuner's choice of a timed run; default: the library's default shape)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the configurations are independent and a "
@@ -607,6 +610,10 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
+        if args.shape:
+            fw, fm, am = (int(x) for x in args.shape.split(","))
+            fwd_batch.set_launch_shape(n, fw, fm, am)
+            batch.set_launch_shape(n, fw, fm, am)
         B.build_g0(nconf, geo.n, geo.voff, geo.sites, geo.tau, w.L, w.t, w.beta, mu, alpha, geo.Goff, G, dG, stream)
         fwd_batch.forward(G, geo.Goff, None, -1.0, S, stream)
         batch.adjoint(G, geo.Goff, stub, -1.0, obar, S, Gb, sb, stream)
