@@ -286,7 +286,7 @@ cos_status cos_batch_adjoint_plan(cos_batch_t b, int32_t n, int32_t *split_level
 /* Autotuner (Results, GPU parallelization: launch shape per problem size).
  * For every order in the batch, times the level kernels over the caller's
  * inputs for each candidate launch shape -- wavefronts per workgroup of the
- * forward kernel (4, 8; 8, 16 with COS_F_SUBLATTICE) and the most masks
+ * forward kernel (4, 8, 16; 8, 16 with COS_F_SUBLATTICE) and the most masks
  * (state-table tiles) per wavefront of the forward (1, 2, 4, 8, 16) and, when
  * d_out_bar is not NULL, of the reverse kernel (2, 4, 6, 8, 12, 16, 24, 32, 48, 64;
  * a reverse level is cut into as few rounds of one workgroup per CU as that
@@ -304,8 +304,8 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
 cos_status cos_batch_launch_shape(cos_batch_t b, int32_t n, int32_t *fwd_waves,
                                   int32_t *fwd_masks, int32_t *adj_masks);
 /* Set the launch shape of order n instead of tuning it (for instance one that
- * cos_batch_autotune found before): fwd_waves in [1, 8] ([1, 16] with
- * COS_F_SUBLATTICE), fwd_masks in [1, 16], adj_masks in [1, 64] (the forward clamps
+ * cos_batch_autotune found before): fwd_waves in [1, 16], fwd_masks in
+ * [1, 16], adj_masks in [1, 64] (the forward clamps
  * its masks per wavefront to 4 with several flavour slots).  COS_EINVAL for
  * values outside these ranges or an order the batch does not have. */
 cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_waves, int32_t fwd_masks,

@@ -170,7 +170,7 @@ __device__ __forceinline__ bool empty_plane(int u, int lam, uint32_t twos) {
 }
 
 template <int N, bool MULTI, bool MASK>
-__global__ void __launch_bounds__(512) level_fwd_kernel(const LvlArgs A) {
+__global__ void __launch_bounds__(1024) level_fwd_kernel(const LvlArgs A) {
     extern __shared__ double lds[];
     double *Gs_all = lds;                      // [N * N][64]
     const int lane = threadIdx.x & 63, wave = COS_RF(threadIdx.x >> 6);   // wave index: uniform
@@ -648,7 +648,7 @@ static hipError_t allow_lds(const void *fn, size_t bytes) {
 
 hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s) {
     const int n = a.plan.n;
-    if (!reverse && (wpb < 1 || wpb > 8)) return hipErrorInvalidValue;
+    if (!reverse && (wpb < 1 || wpb > 16)) return hipErrorInvalidValue;
     if (reverse) {
         const int wpa = adj_waves_per_block();
         if (wpb != wpa) return hipErrorInvalidValue;

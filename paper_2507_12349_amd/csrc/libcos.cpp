@@ -1128,7 +1128,7 @@ cos_status cos_batch_autotune(cos_batch_t b, const double *d_G, const int64_t *d
     hipStream_t s = (hipStream_t)stream;
     const bool was_timing = b->timing;
     b->timing = false;
-    static const int kWaves[] = {4, 8}, kSubWaves[] = {8, 16};
+    static const int kWaves[] = {4, 8, 16}, kSubWaves[] = {8, 16, 16};   // (16 twice: arrays of one size)
     static const int kCaps[] = {1, 2, 4, 8, 16};
     static const int kAdjCaps[] = {2, 4, 6, 8, 12, 16, 24, 32, 48, 64};
     for (OrderGroup &o : b->orders) {
@@ -1189,8 +1189,7 @@ cos_status cos_batch_set_launch_shape(cos_batch_t b, int32_t n, int32_t fwd_wave
     if (!b) return fail(COS_EINVAL, "batch handle is NULL");
     for (OrderGroup &o : b->orders)
         if (o.n == n) {
-            const int wmax = o.sub ? 16 : 8;
-            if (fwd_waves < 1 || fwd_waves > wmax) return fail(COS_EINVAL, "fwd_waves must be in [1, %d]", wmax);
+            if (fwd_waves < 1 || fwd_waves > 16) return fail(COS_EINVAL, "fwd_waves must be in [1, 16]");
             if (fwd_masks < 1 || fwd_masks > 16 || adj_masks < 1 || adj_masks > 64)
                 return fail(COS_EINVAL, "fwd_masks must be in [1, 16] and adj_masks in [1, 64]");
             o.shape.fwd_wpb = fwd_waves;

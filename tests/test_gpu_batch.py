@@ -257,7 +257,7 @@ def test_autotune_keeps_results():
     b.autotune(G, Goff, st, -1.0, S1, ob, torch.empty_like(G), torch.empty_like(st))
     shapes = {k: b.launch_shape(k) for k in (4, 7, 9)}
     for k, sh in shapes.items():
-        assert sh["fwd_waves"] in (4, 8) and sh["fwd_masks"] in (1, 2, 4, 8, 16), sh
+        assert sh["fwd_waves"] in (4, 8, 16) and sh["fwd_masks"] in (1, 2, 4, 8, 16), sh
         assert sh["adj_masks"] in (2, 4, 6, 8, 12, 16, 24, 32, 48, 64), sh
     with pytest.raises(B.CosError):
         b.launch_shape(5)
@@ -311,7 +311,7 @@ def test_set_launch_shape_keeps_sums():
     b = B.Batch(n, 3, 1)
     ref = torch.empty(len(mats), dtype=torch.float64, device="cuda:0")
     b.forward(G, Goff, None, -1.0, ref)
-    for waves, masks in ((1, 1), (4, 16), (8, 2)):
+    for waves, masks in ((1, 1), (4, 16), (8, 2), (16, 4), (12, 3)):
         for k in (5, 9):
             b.set_launch_shape(k, waves, masks, 4)
             assert b.launch_shape(k)["fwd_waves"] == waves
@@ -319,7 +319,7 @@ def test_set_launch_shape_keeps_sums():
         b.forward(G, Goff, None, -1.0, out)
         torch.cuda.synchronize()
         assert torch.equal(out, ref), (waves, masks)
-    for bad in ((0, 4, 4), (9, 4, 4), (8, 0, 4), (8, 17, 4), (8, 4, 65)):
+    for bad in ((0, 4, 4), (17, 4, 4), (8, 0, 4), (8, 17, 4), (8, 4, 65)):
         with pytest.raises(B.CosError):
             b.set_launch_shape(5, *bad)
     with pytest.raises(B.CosError):
