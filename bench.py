@@ -304,9 +304,10 @@ def _refs_stats(name, S_host, idx_all=None):
             "kappa_max": float(kappa.max()), "configs_kappa_gt_1e5": int((~low).sum())}
 
 
-def _cpu_forward_rate(d, idx, threads, variant, nflav, stubs_of):
+def _cpu_forward_rate(d, idx, threads, variant, nflav, stubs_of, per_config=None):
     """Oracle DP (float64) forward sums of configurations idx, one per thread:
-    configurations per second and wall time."""
+    configurations per second and wall time.  per_config, a dict, receives each
+    configuration's own time on its thread."""
     from concurrent.futures import ThreadPoolExecutor
 
     import oracle
@@ -322,7 +323,11 @@ def _cpu_forward_rate(d, idx, threads, variant, nflav, stubs_of):
         mats[c] = G[0] if variant == 0 else G
 
     def one(c):
-        return oracle.dp(mats[c], nflav, variant, stubs_of(c), -1.0, precision="d")
+        t = time.perf_counter()
+        r = oracle.dp(mats[c], nflav, variant, stubs_of(c), -1.0, precision="d")
+        if per_config is not None:
+            per_config[c] = time.perf_counter() - t
+        return r
 
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
@@ -475,30 +480,30 @@ def workload_legs(B, torch, reps, cpu_threads=0, only=None):
         leg["vs_oracle_refs"] = _refs_stats(name, S_host)
         if cpu_threads:
             if name == "uneven":
-                # one configuration of each order, concurrently; extrapolated to the batch's order mix
-                per = {}
-                for k in range(6, 13):
-                    c = int(np.nonzero(d.n == k)[0][0])
-                    per[k] = c
-                from concurrent.futures import ThreadPoolExecutor
+                # a seeded subsample per order (the batch's first configurations of that
+                # order), timed configuration by configuration on all cores, largest orders
+                # first; the per-order mean single-thread time is extrapolated to the batch's
+                # order mix.  64 per order up to n = 10; fewer at n = 11, 12 (5 and 19 s each)
+                # so that the run stays within about half a minute.
+                take = {k: (64 if k <= 10 else 32 if k == 11 else 8) for k in range(6, 13)}
+                idx = []
+                for k in range(12, 5, -1):
+                    idx += [int(c) for c in np.nonzero(d.n == k)[0][:take[k]]]
                 sig = d.delta[:nmat] / w.U
-
-                def order_time(k):
-                    t0 = time.perf_counter()
-                    _cpu_forward_rate(d, [per[k]], 1, w.variant, w.nflav, lambda c: sig)
-                    return k, time.perf_counter() - t0
-
-                t0 = time.perf_counter()
-                with ThreadPoolExecutor(max_workers=7) as ex:
-                    tk = dict(ex.map(order_time, range(6, 13)))
-                wall = time.perf_counter() - t0
+                tc = {}
+                _, wall = _cpu_forward_rate(d, idx, cpu_threads, w.variant, w.nflav, lambda c: sig,
+                                            per_config=tc)
+                tk = {k: float(np.mean([tc[c] for c in idx if int(d.n[c]) == k])) for k in range(6, 13)}
                 core_s = sum(tk[k] * int((d.n == k).sum()) for k in tk)
                 leg["cpu_oracle"] = {"configs_per_s": nconf / (core_s / cpu_threads), "cores": cpu_threads,
                                      "kind": "oracle, extrapolated",
-                                     "sample": "one configuration of each order 6..12 timed (%.0f s wall), "
-                                               "per-order single-core times x the batch's order counts / %d cores"
-                                               % (wall, cpu_threads),
-                                     "single_core_s_per_order": {int(k): v for k, v in tk.items()}}
+                                     "sample": "%s configurations of orders 6..12 (%d in all, %.0f s wall on %d "
+                                               "threads); mean time per configuration and order x the batch's "
+                                               "order counts / %d cores"
+                                               % ("/".join(str(take[k]) for k in range(6, 13)), len(idx), wall,
+                                                  cpu_threads, cpu_threads),
+                                     "configs_per_order_timed": {int(k): take[k] for k in range(6, 13)},
+                                     "s_per_config_per_order": {int(k): v for k, v in tk.items()}}
             else:
                 k = {"plain_single": 1, "plain_batch": 256, "sym_broken": 48}[name]
                 rate, dt = _cpu_forward_rate(d, list(range(k)), cpu_threads, w.variant, w.nflav, lambda c: None)
