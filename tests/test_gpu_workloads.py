@@ -4,8 +4,10 @@ pipeline vs the oracle run on the oracle's own propagators.  Full batches run
 on the GPU in the launch configuration the benchmark uses; sampled
 configurations are checked one by one against the oracle (long double).
 
-Tolerance: relative 1e-10, or the FP64 bound 8 n (n + 2) eps S_abs where a
-configuration's cancellation (kappa = S_abs / |S|) makes that the larger."""
+Gate: relative 1e-10 for every sampled configuration.  The FP64 bound
+8 n (n + 2) eps S_abs (kappa = S_abs / |S| measures the cancellation) is printed
+beside it; it replaces the gate only for the named exceptions, configurations
+whose cancellation lets FP64 rounding alone exceed 1e-10."""
 import numpy as np
 import pytest
 
@@ -14,6 +16,8 @@ from paper_2507_12349_amd.workloads import draw
 
 pytestmark = pytest.mark.gpu
 EPS = np.finfo(np.float64).eps
+# kappa 2.8e9: measured 1.4e-10 relative, 2.3e-7 of its FP64 bound
+EXCEPTIONS = {("sym_broken", 96)}
 
 
 def _check_sample(oracle_mod, d, res, idx):
@@ -31,11 +35,14 @@ def _check_sample(oracle_mod, d, res, idx):
         sa = oracle_mod.dp(np.abs(oracle_args(Go, res["variant"])), res["nflav"], res["variant"],
                            None if st is None else -np.abs(st), 1.0)
         err = abs(res["S"][c] - ref)
-        bound = max(1e-10 * abs(ref), 8 * n * (n + 2) * EPS * sa)
-        print("  config %d n=%d S=%.6e ref=%.6e rel=%.2e kappa=%.1e" % (c, n, res["S"][c], ref,
-              err / abs(ref), sa / abs(ref)), flush=True)
-        assert err <= bound, (c, n, res["S"][c], ref)
-        worst = max(worst, err / abs(ref))
+        bound = 8 * n * (n + 2) * EPS * sa
+        exc = (w.name, int(c)) in EXCEPTIONS
+        print("  config %d n=%d S=%.6e ref=%.6e rel=%.2e kappa=%.1e err/FP64 bound=%.1e%s"
+              % (c, n, res["S"][c], ref, err / abs(ref), sa / abs(ref), err / bound,
+                 " (named exception)" if exc else ""), flush=True)
+        assert err <= (bound if exc else 1e-10 * abs(ref)), (c, n, res["S"][c], ref)
+        if not exc:
+            worst = max(worst, err / abs(ref))
     return worst
 
 
@@ -96,8 +103,9 @@ def test_adjoint_workload_forward(oracle_mod):
 
 def test_uneven_full(oracle_mod):
     """All 8192 configurations of the uneven SU(6) shift workload in one batch
-    (orders 6..12, one group of launches per order, the largest orders in
-    chunks of groups): every sum finite; the first 512 bitwise equal to the
+    (orders 6..12, one group of launches per order, order 12 in chunks of
+    groups where the workspace limit asks for it, orders 11..6 on the
+    library's side stream beside order 12): every sum finite; the first 512 bitwise equal to the
     same configurations run as a batch of their own (a configuration's sum does
     not depend on the rest of the batch); samples of every order up to 11
     against the oracle."""
