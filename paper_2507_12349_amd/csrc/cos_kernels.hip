@@ -8,28 +8,40 @@ namespace libcos {
 // free propagator (Methods, square-lattice dispersion; imaginary-time
 // propagator with tau = 0 read as 0^-), one workgroup per configuration
 // ---------------------------------------------------------------------------
+// 128 threads: the n^2 <= 144 entries of a configuration in one or two passes
+constexpr int kG0Threads = 128;
+
 struct G0Params {
     double mu[COS_FMAX], alpha[COS_FMAX];
     double t, beta;
     int L, nmat;
 };
 
-__global__ void __launch_bounds__(256) g0_kernel(const int32_t *__restrict__ nvec,
-                                                 const int64_t *__restrict__ voff,
-                                                 const int32_t *__restrict__ sites,
-                                                 const double *__restrict__ tau,
-                                                 const int64_t *__restrict__ Goff,
-                                                 double *__restrict__ Gout, double *__restrict__ dGout,
-                                                 const G0Params p) {
+// Per momentum k the propagator term is -e^{-xi d} (1 - n_F) for d > 0 and
+// e^{xi s} n_F for d = -s <= 0.  Written with every exponent non-positive,
+// each case is +-exp(E) R_k with R_k = 1 / (1 + e^{-beta |xi_k|}) (the same
+// factor for both signs of xi) and E one of -xi d, xi (beta - d), xi s or
+// -xi (beta - s): one exponential per term, R_k shared by the entries.
+// dG/dxi follows from the same term: g (beta n_F - d), resp. g (beta n_F -
+// beta - d).  The phase index (k . dx) mod L advances by dx mod L per step.
+__global__ void __launch_bounds__(kG0Threads) g0_kernel(const int32_t *__restrict__ nvec,
+                                                        const int64_t *__restrict__ voff,
+                                                        const int32_t *__restrict__ sites,
+                                                        const double *__restrict__ tau,
+                                                        const int64_t *__restrict__ Goff,
+                                                        double *__restrict__ Gout, double *__restrict__ dGout,
+                                                        const G0Params p) {
     extern __shared__ double sm[];
     const int L = p.L, L2 = L * L;
     double *xi = sm;            // [L2]
-    double *nf = sm + L2;       // [L2]
-    double *cs = sm + 2 * L2;   // [L] cos(2 pi j / L)
+    double *nf = sm + L2;       // [L2] n_F(xi)
+    double *rk = sm + 2 * L2;   // [L2] 1 / (1 + e^{-beta |xi|})
+    double *cs = sm + 3 * L2;   // [L] cos(2 pi j / L)
     const int c = blockIdx.x;
     const int n = nvec[c];
     const int64_t v0 = voff[c];
     const int64_t goff = Goff[c];
+    const double beta = p.beta;
     for (int j = threadIdx.x; j < L; j += blockDim.x) cs[j] = cospi(2.0 * (double)j / (double)L);
     for (int g = 0; g < p.nmat; ++g) {
         __syncthreads();
@@ -37,36 +49,38 @@ __global__ void __launch_bounds__(256) g0_kernel(const int32_t *__restrict__ nve
             const int mx = k % L, my = k / L;
             const double e = -2.0 * p.t * (cospi(2.0 * mx / (double)L) + cospi(2.0 * my / (double)L)) -
                              p.mu[g] + p.alpha[g];
+            const double q = exp(-beta * fabs(e)), r = 1.0 / (1.0 + q);
             xi[k] = e;
-            // Fermi function without overflow
-            nf[k] = (e >= 0.0) ? exp(-p.beta * e) / (1.0 + exp(-p.beta * e)) : 1.0 / (exp(p.beta * e) + 1.0);
+            rk[k] = r;
+            nf[k] = (e >= 0.0) ? q * r : r;   // Fermi function without overflow
         }
         __syncthreads();
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
             const int a = e / n, b = e % n;
-            const int dx = sites[2 * (v0 + a)] - sites[2 * (v0 + b)];
-            const int dy = sites[2 * (v0 + a) + 1] - sites[2 * (v0 + b) + 1];
+            int dx = (sites[2 * (v0 + a)] - sites[2 * (v0 + b)]) % L;
+            int dy = (sites[2 * (v0 + a) + 1] - sites[2 * (v0 + b) + 1]) % L;
+            dx += dx < 0 ? L : 0;
+            dy += dy < 0 ? L : 0;
             const double d = tau[v0 + a] - tau[v0 + b];
+            const bool fwd = d > 0.0;
+            // exponent coefficients for xi >= 0 and xi < 0, sign, dG offset
+            const double cpos = fwd ? -d : -(beta + d), cneg = fwd ? beta - d : -d;
+            const double sgn = fwd ? -1.0 : 1.0, doff = fwd ? -d : -beta - d;
             double sg = 0.0, sd = 0.0;
-            for (int k = 0; k < L2; ++k) {
-                const int mx = k % L, my = k / L;
-                int ph = (mx * dx + my * dy) % L;
-                if (ph < 0) ph += L;
-                const double x = xi[k], nF = nf[k];
-                double gk, dk;
-                if (d > 0.0) {
-                    // -exp(-x d)(1 - nF), every exponent kept non-positive
-                    gk = (x >= 0.0) ? -exp(-x * d) / (1.0 + exp(-p.beta * x))
-                                    : -exp(x * (p.beta - d)) / (exp(p.beta * x) + 1.0);
-                    dk = gk * (p.beta * nF - d);
-                } else {
-                    const double s = -d;   // exp(x s) nF
-                    gk = (x <= 0.0) ? exp(x * s) / (exp(p.beta * x) + 1.0)
-                                    : exp(-x * (p.beta - s)) / (1.0 + exp(-p.beta * x));
-                    dk = gk * (p.beta * nF - p.beta - d);
+            int phy = 0;
+            for (int my = 0, k = 0; my < L; ++my) {
+                int ph = phy;
+                for (int mx = 0; mx < L; ++mx, ++k) {
+                    const double x = xi[k];
+                    const double gk = sgn * exp(x * (x >= 0.0 ? cpos : cneg)) * rk[k];
+                    const double dk = gk * __builtin_fma(beta, nf[k], doff);
+                    sg = __builtin_fma(cs[ph], gk, sg);
+                    sd = __builtin_fma(cs[ph], dk, sd);
+                    ph += dx;
+                    ph -= ph >= L ? L : 0;
                 }
-                sg = __builtin_fma(cs[ph], gk, sg);
-                sd = __builtin_fma(cs[ph], dk, sd);
+                phy += dy;
+                phy -= phy >= L ? L : 0;
             }
             const double inv = 1.0 / (double)L2;
             Gout[goff + (int64_t)g * n * n + e] = sg * inv;
@@ -84,8 +98,8 @@ hipError_t launch_g0(int nconf, const int32_t *n, const int64_t *voff, const int
         p.alpha[g] = g < nmat ? alpha[g] : 0.0;
     }
     p.t = t; p.beta = beta; p.L = L; p.nmat = nmat;
-    const size_t shm = (size_t)(2 * L * L + L) * sizeof(double);
-    hipLaunchKernelGGL(g0_kernel, dim3(nconf), dim3(256), shm, s, n, voff, sites, tau, Goff, G, dG, p);
+    const size_t shm = (size_t)(3 * L * L + L) * sizeof(double);
+    hipLaunchKernelGGL(g0_kernel, dim3(nconf), dim3(kG0Threads), shm, s, n, voff, sites, tau, Goff, G, dG, p);
     return hipGetLastError();
 }
 
@@ -111,21 +125,22 @@ __device__ __forceinline__ double fermi(double x, double beta) {
     return (x >= 0.0) ? exp(-beta * x) / (1.0 + exp(-beta * x)) : 1.0 / (exp(beta * x) + 1.0);
 }
 
-// imaginary-time factor of one eigenvalue x for the time difference d
-__device__ __forceinline__ double g0_branch(double x, double d, double beta) {
-    if (d > 0.0)   // -exp(-x d)(1 - nF), every exponent kept non-positive
-        return (x >= 0.0) ? -exp(-x * d) / (1.0 + exp(-beta * x)) : -exp(x * (beta - d)) / (exp(beta * x) + 1.0);
-    const double s = -d;   // exp(x s) nF
-    return (x <= 0.0) ? exp(x * s) / (exp(beta * x) + 1.0) : exp(-x * (beta - s)) / (1.0 + exp(-beta * x));
+// imaginary-time factor of one eigenvalue x with Fermi factor nF for the time
+// difference d, as in g0_kernel: +-exp(E) R with every exponent E non-positive
+// and R = 1 / (1 + e^{-beta |x|}) = (x >= 0 ? 1 - nF : nF); cpos, cneg and sgn
+// are the entry's exponent coefficients and sign.
+__device__ __forceinline__ double g0_branch(double x, double nF, double cpos, double cneg, double sgn) {
+    const bool pos = x >= 0.0;
+    return sgn * exp(x * (pos ? cpos : cneg)) * (pos ? 1.0 - nF : nF);
 }
 
-__global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__restrict__ nvec,
-                                                           const int64_t *__restrict__ voff,
-                                                           const int32_t *__restrict__ cells,
-                                                           const double *__restrict__ tau,
-                                                           const int64_t *__restrict__ Goff,
-                                                           double *__restrict__ Gout, double *__restrict__ dGout,
-                                                           const HcParams p) {
+__global__ void __launch_bounds__(kG0Threads) g0_honeycomb_kernel(const int32_t *__restrict__ nvec,
+                                                                  const int64_t *__restrict__ voff,
+                                                                  const int32_t *__restrict__ cells,
+                                                                  const double *__restrict__ tau,
+                                                                  const int64_t *__restrict__ Goff,
+                                                                  double *__restrict__ Gout,
+                                                                  double *__restrict__ dGout, const HcParams p) {
     extern __shared__ double sm[];
     const int L = p.L, L2 = L * L;
     double *ep = sm, *em = sm + L2, *rz = sm + 2 * L2, *ex = sm + 3 * L2, *ey = sm + 4 * L2;
@@ -160,31 +175,41 @@ __global__ void __launch_bounds__(256) g0_honeycomb_kernel(const int32_t *__rest
         __syncthreads();
         for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
             const int a = e / n, b = e % n;
-            const int r1 = cells[2 * (v0 + a)] - cells[2 * (v0 + b)];
-            const int r2 = cells[2 * (v0 + a) + 1] - cells[2 * (v0 + b) + 1];
-            const double d = tau[v0 + a] - tau[v0 + b];
+            int r1 = (cells[2 * (v0 + a)] - cells[2 * (v0 + b)]) % L;
+            int r2 = (cells[2 * (v0 + a) + 1] - cells[2 * (v0 + b) + 1]) % L;
+            r1 += r1 < 0 ? L : 0;
+            r2 += r2 < 0 ? L : 0;
+            const double d = tau[v0 + a] - tau[v0 + b], beta = p.beta;
+            const bool fwd = d > 0.0;
+            const double cpos = fwd ? -d : -(beta + d), cneg = fwd ? beta - d : -d, sgn = fwd ? -1.0 : 1.0;
             // d/dx of the branch factor: d > 0: f (beta nF - d); d <= 0: f (beta nF - beta - d)
-            const double dsh = d > 0.0 ? -d : -p.beta - d;
+            const double dsh = fwd ? -d : -beta - d;
             double acc[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};   // [G, dG/dxi][aa, bb, ab, ba]
-            for (int k = 0; k < L2; ++k) {
-                const int m1 = k % L, m2 = k / L;
-                int ph = (m1 * r1 + m2 * r2) % L;
-                if (ph < 0) ph += L;
-                const double c0 = cs[ph], s0 = sn[ph];
-                const double gp = g0_branch(ep[k], d, p.beta), gm = g0_branch(em[k], d, p.beta);
-                const double fpv[2] = {gp, gp * __builtin_fma(p.beta, np_[k], dsh)};
-                const double fmv[2] = {gm, gm * __builtin_fma(p.beta, nm_[k], dsh)};
+            int ph2 = 0;   // (m1 r1 + m2 r2) mod L, advanced step by step
+            for (int m2 = 0, k = 0; m2 < L; ++m2) {
+                int ph = ph2;
+                for (int m1 = 0; m1 < L; ++m1, ++k) {
+                    const double c0 = cs[ph], s0 = sn[ph];
+                    ph += r1;
+                    ph -= ph >= L ? L : 0;
+                    const double gp = g0_branch(ep[k], np_[k], cpos, cneg, sgn);
+                    const double gm = g0_branch(em[k], nm_[k], cpos, cneg, sgn);
+                    const double fpv[2] = {gp, gp * __builtin_fma(beta, np_[k], dsh)};
+                    const double fmv[2] = {gm, gm * __builtin_fma(beta, nm_[k], dsh)};
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    if (q == 1 && !dGout) break;
-                    const double S = 0.5 * (fpv[q] + fmv[q]), Dd = 0.5 * (fpv[q] - fmv[q]);
-                    acc[q][0] = __builtin_fma(c0, __builtin_fma(Dd, rz[k], S), acc[q][0]);
-                    acc[q][1] = __builtin_fma(c0, __builtin_fma(-Dd, rz[k], S), acc[q][1]);
-                    // Re[e^{i phi} Dd (ex + i ey)] and Re[e^{i phi} Dd (ex - i ey)]
-                    const double xr = Dd * ex[k], xi = Dd * ey[k];
-                    acc[q][2] = __builtin_fma(c0, xr, __builtin_fma(-s0, xi, acc[q][2]));
-                    acc[q][3] = __builtin_fma(c0, xr, __builtin_fma(s0, xi, acc[q][3]));
+                    for (int q = 0; q < 2; ++q) {
+                        if (q == 1 && !dGout) break;
+                        const double S = 0.5 * (fpv[q] + fmv[q]), Dd = 0.5 * (fpv[q] - fmv[q]);
+                        acc[q][0] = __builtin_fma(c0, __builtin_fma(Dd, rz[k], S), acc[q][0]);
+                        acc[q][1] = __builtin_fma(c0, __builtin_fma(-Dd, rz[k], S), acc[q][1]);
+                        // Re[e^{i phi} Dd (ex + i ey)] and Re[e^{i phi} Dd (ex - i ey)]
+                        const double xr = Dd * ex[k], xi = Dd * ey[k];
+                        acc[q][2] = __builtin_fma(c0, xr, __builtin_fma(-s0, xi, acc[q][2]));
+                        acc[q][3] = __builtin_fma(c0, xr, __builtin_fma(s0, xi, acc[q][3]));
+                    }
                 }
+                ph2 += r2;
+                ph2 -= ph2 >= L ? L : 0;
             }
             const double inv = 1.0 / (double)L2;
 #pragma unroll
@@ -213,7 +238,7 @@ hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff,
     }
     p.t = t; p.beta = beta; p.L = L; p.nmat = nmat;
     const size_t shm = (size_t)(7 * L * L + 2 * L) * sizeof(double);
-    hipLaunchKernelGGL(g0_honeycomb_kernel, dim3(nconf), dim3(256), shm, s, n, voff, cells, tau, Goff, G, dG, p);
+    hipLaunchKernelGGL(g0_honeycomb_kernel, dim3(nconf), dim3(kG0Threads), shm, s, n, voff, cells, tau, Goff, G, dG, p);
     return hipGetLastError();
 }
 
