@@ -27,5 +27,5 @@ def test_counts_match_exponential_formula():
         announce("integer counts, weight %s per cycle, n = 1..12" % x)
         for n, ref in enumerate(seq, start=1):
             assert B.connected_count(n, int(x)) == _signed64(int(ref)), (x, n)
-    # the survey's value for x = +1, n = 10 (beyond FP64's exact range)
+    # x = +1, n = 10 written out (above 2^53: beyond FP64's exact range)
     assert B.connected_count(10, 1) == 2281153623146496000
