@@ -243,29 +243,41 @@ hipError_t launch_g0_honeycomb(int nconf, const int32_t *n, const int64_t *voff,
 }
 
 // ---------------------------------------------------------------------------
-// chain rule to mu and the shift, one thread per (configuration, matrix)
+// chain rule to mu and the shift: x = sum_jk dS/dG[j][k] dG/dxi[j][k] per
+// (configuration, matrix), mu_bar = -x, alpha_bar = x + sigma_bar / U.  One
+// wavefront per (configuration, matrix): the lanes read the n^2 entries
+// coalesced and a butterfly over the 64 lanes sums their partial products
+// (a fixed order, so repeated calls agree bit for bit).
 // ---------------------------------------------------------------------------
-__global__ void chain_kernel(int nconf, const int32_t *__restrict__ nvec, int nmat,
-                             const int64_t *__restrict__ Goff, const double *__restrict__ Gb,
-                             const double *__restrict__ dG, const double *__restrict__ sb, int nstub,
-                             double U, double *__restrict__ mub, double *__restrict__ alb) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nconf * nmat) return;
-    const int c = i / nmat, g = i % nmat;
-    const int n = nvec[c];
-    const int64_t base = Goff[c] + (int64_t)g * n * n;
-    double x = 0.0;
-    for (int e = 0; e < n * n; ++e) x = __builtin_fma(Gb[base + e], dG[base + e], x);
-    mub[i] = -x;
-    alb[i] = x + (sb ? sb[(int64_t)c * nstub + (nstub == 1 ? 0 : g)] / U : 0.0);
+__global__ void __launch_bounds__(256) chain_kernel(int nconf, const int32_t *__restrict__ nvec, int nmat,
+                                                    const int64_t *__restrict__ Goff, const double *__restrict__ Gb,
+                                                    const double *__restrict__ dG, const double *__restrict__ sb,
+                                                    int nstub, double U, double *__restrict__ mub,
+                                                    double *__restrict__ alb) {
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)nconf * nmat, stride = (int64_t)gridDim.x * (blockDim.x >> 6);
+    // wid is uniform in a wavefront: whole wavefronts leave the loop together
+    for (int64_t wid = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wid < nw; wid += stride) {
+        const int c = (int)(wid / nmat), g = (int)(wid % nmat);
+        const int n = nvec[c];
+        const int64_t base = Goff[c] + (int64_t)g * n * n;
+        double x = 0.0;
+        for (int e = lane; e < n * n; e += 64) x = __builtin_fma(Gb[base + e], dG[base + e], x);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (lane == 0) {
+            mub[wid] = -x;
+            alb[wid] = x + (sb ? sb[(int64_t)c * nstub + (nstub == 1 ? 0 : g)] / U : 0.0);
+        }
+    }
 }
 
 hipError_t launch_chain(int nconf, const int32_t *n, int nmat, const int64_t *Goff, const double *Gb,
                         const double *dG, const double *sb, int nstub, double U, double *mub,
                         double *alb, hipStream_t s) {
-    const int tot = nconf * nmat;
-    hipLaunchKernelGGL(chain_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, nconf, n, nmat, Goff, Gb,
-                       dG, sb, nstub, U, mub, alb);
+    const int64_t blocks = ((int64_t)nconf * nmat + 3) / 4;   // four wavefronts per workgroup
+    hipLaunchKernelGGL(chain_kernel, dim3((unsigned)std::min<int64_t>(blocks, 1 << 20)), dim3(256), 0, s, nconf, n,
+                       nmat, Goff, Gb, dG, sb, nstub, U, mub, alb);
     return hipGetLastError();
 }
 
