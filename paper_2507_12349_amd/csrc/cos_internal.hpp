@@ -132,6 +132,7 @@ struct LvlArgs {
     int32_t level, group0, nfs, stubs, mpb;
     int32_t mask_only;        // SU(2) mask-only rules (two spin blocks as the two planes)
     int32_t det_groups;       // deterministic reverse: groups of the order (stride of the partial sums)
+    int32_t row_items;        // reverse: the work items are (mask, row) pairs, not masks (levels of few masks)
     double W;                 // factor of one closed cycle: w * nflav (uniform) or w
     double *out;              // forward, last level: S per configuration (may be null)
     const double *out_bar;    // reverse: dL/dS per configuration
@@ -148,8 +149,9 @@ hipError_t launch_zero(double *p, int64_t n, hipStream_t s);
 hipError_t launch_sub_level(const LvlArgs &a, int nblocks, int ngroups, int wpb, hipStream_t s);
 // sublattice reverse level: adj_waves_per_block() wavefronts per workgroup
 hipError_t launch_sub_adj_level(const LvlArgs &a, int nblocks, int ngroups, hipStream_t s);
-// nblocks = blocks of `a.mpb` masks; `wpb` wavefronts per workgroup (forward:
-// at most 8; reverse: adj_waves_per_block())
+// nblocks = blocks of `a.mpb` masks (reverse with row_items: of (mask, row)
+// items); `wpb` wavefronts per workgroup (forward: at most 16; reverse:
+// adj_waves_per_block())
 hipError_t launch_level(const LvlArgs &a, bool reverse, int nblocks, int ngroups, int wpb, hipStream_t s);
 int adj_waves_per_block();
 // deterministic reverse sweep: every level's masks in kDetParts fixed parts;

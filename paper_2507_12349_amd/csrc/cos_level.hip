@@ -356,9 +356,13 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
     // the workgroup's block of masks; its wavefronts claim masks one at a time
-    // from an LDS counter, so that a wavefront that drew short rows takes more
+    // from an LDS counter, so that a wavefront that drew short rows takes more.
+    // On levels of few masks the items are (mask, row) pairs instead, item
+    // i = N m + k standing for row k of mask m, so that the rows of a mask run
+    // side by side rather than one after another in one wavefront.
+    const int nitems = A.row_items ? L.w * N : L.w;
     const int blk0 = blockIdx.x * wpb * A.mpb;
-    const int blk1 = min(blk0 + wpb * A.mpb, L.w);   // may hold fewer masks than waves: they still join the barriers
+    const int blk1 = min(blk0 + wpb * A.mpb, nitems);   // may hold fewer items than waves: they still join the barriers
     __shared__ int next_mask;
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
@@ -385,35 +389,50 @@ __global__ void __launch_bounds__(1024) level_adj_kernel(const LvlArgs A) {
         const double sg = A.stubs ? A.sigT[(int64_t)(g * nfs + lam) * 64 + lane] : 0.0;
         double sacc = 0.0;
         bool any = false;
-        for (int mi = blk0 + wave; mi < blk1;) {
+        for (int it = blk0 + wave; it < blk1;) {
             any = true;
+            const int mi = A.row_items ? it / N : it;
             const MaskRec<N> M = load_rec<N>(P, L.z + mi);
             const uint32_t ones = M.ones, twos = M.twos;
-            double tb = 0.0;
-            if (top) {
-                tb = obar;
-            } else if (ones) {
-                const int h = __builtin_ctz(ones);
-                const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
-                for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
-                    tb += lane_ld(Bn + k * cpl + (int64_t)crow * N * 64 + h * 64, lane8);
-            }
-            tb *= A.W;
-            const double sc = (M.code == 1 ? 2.0 : 1.0);
             uint32_t hs = (twos & 1u) ? (twos & ~1u) : 0u;   // heads >= 1, ascending
             int u = 0, slot = 0;
-            while (true) {
-                if (!(MASK && empty_plane(u, lam, twos)))
-                    adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start, tb,
-                                     sg * sc, sc, sacc);
-                if (!hs) break;
-                u = __builtin_ctz(hs);
-                hs &= hs - 1u;
-                ++slot;
+            bool go = true;
+            if (A.row_items) {
+                // this item's row alone: slot k = 0 (head 0) or the k-th head >= 1
+                const int k = it - mi * N;
+                for (int j = 1; j < k; ++j) hs &= hs - 1u;
+                if (k > 0) {
+                    go = hs != 0;   // the mask has fewer rows
+                    u = go ? __builtin_ctz(hs) : 0;
+                    slot = k;
+                }
+                hs = 0;
+            }
+            if (go) {
+                double tb = 0.0;
+                if (top) {
+                    tb = obar;
+                } else if (ones) {
+                    const int h = __builtin_ctz(ones);
+                    const int crow = close_row_base<N>(M, h) + head_slot(h, twos | (1u << h));
+                    for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
+                        tb += lane_ld(Bn + k * cpl + (int64_t)crow * N * 64 + h * 64, lane8);
+                }
+                tb *= A.W;
+                const double sc = (M.code == 1 ? 2.0 : 1.0);
+                while (true) {
+                    if (!(MASK && empty_plane(u, lam, twos)))
+                        adj_row<N, MASK>(M, gaddr, gbaddr, F, Bn, Bc, lane8, fpl, cpl, npl, lam, u, M.rb + slot, start,
+                                         tb, sg * sc, sc, sacc);
+                    if (!hs) break;
+                    u = __builtin_ctz(hs);
+                    hs &= hs - 1u;
+                    ++slot;
+                }
             }
             int nx = 0;
             if (lane == 0) nx = atomicAdd(&next_mask, 1);
-            mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
+            it = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
         if (A.stubs && any) atomicAdd(A.sbar_T + (int64_t)(g * nfs + lam) * 64 + lane, sacc);
         __syncthreads();

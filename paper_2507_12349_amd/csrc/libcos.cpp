@@ -1026,7 +1026,13 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                 a.F_frows = srows;
                 a.F_row0 = (int32_t)srow(l, upper);
                 const int nm = o.hp->levels[l].w;
-                a.mpb = adj_masks(o.shape, nm, cg, b->ncu);
+                // a level whose masks fill at most half the wavefronts of one
+                // round, and whose masks hold at least n / 2 rows on average
+                // (the upper levels), gives every row a wavefront of its own
+                a.row_items = (!o.sub && (int64_t)nm * cg * 2 <= (int64_t)b->ncu * 16 &&
+                               2 * level_rows(*o.hp, l, l) >= (int64_t)nm * o.n) ? 1 : 0;
+                const int items = a.row_items ? nm * o.n : nm;
+                a.mpb = adj_masks(o.shape, items, cg, b->ncu);
                 a.out_bar = d_out_bar;
                 a.Gbar_T = GbT;
                 a.sbar_T = sbT;
@@ -1038,7 +1044,7 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                     continue;
                 }
                 if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
-                else LAUNCH_TRY(launch_level(a, true, (nm + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
+                else LAUNCH_TRY(launch_level(a, true, (items + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
             }
             return COS_OK;
         };
