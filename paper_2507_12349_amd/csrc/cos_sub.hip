@@ -325,9 +325,14 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
     const int i0 = SubAdjShape<N>::SPLIT ? (int)blockIdx.z * RI : 0;   // first owned row i
     const DevPlan &P = A.plan;
     const int4 L = load_level(P, A.level);
-    // the workgroup's block of masks, claimed one at a time by its wavefronts
+    // the workgroup's block of masks, claimed one at a time by its wavefronts;
+    // on levels of few masks the items are (mask, row) pairs instead, item
+    // i = 2n m + k standing for row k of mask m (a mask has at most 2n rows),
+    // so that the rows of a mask run side by side
+    constexpr int RPM = D;
+    const int nitems = A.row_items ? L.w * RPM : L.w;
     const int blk0 = blockIdx.x * wpb * A.mpb;
-    const int blk1 = min(blk0 + wpb * A.mpb, L.w);   // may hold fewer masks than waves: they still join the barriers
+    const int blk1 = min(blk0 + wpb * A.mpb, nitems);   // may hold fewer items than waves: they still join the barriers
     __shared__ int next_mask;
     const int gl = blockIdx.y, g = A.group0 + gl;
     const int nfs = A.nfs;
@@ -353,40 +358,65 @@ __global__ void __launch_bounds__(1024) sub_adj_kernel(const LvlArgs A) {
         const double *__restrict__ FL = F + lam * fpl;
         const double *__restrict__ BnL = Bn + lam * cpl;
         double *__restrict__ BcL = Bc + lam * npl;
-        for (int mi = blk0 + wave; mi < blk1;) {
+        for (int it = blk0 + wave; it < blk1;) {
+            const int mi = A.row_items ? it / RPM : it;
             const SubRec<N> M = load_sub_rec<N>(P, L.z + mi);
             const uint32_t ones = M.ones, twos = M.twos;
-            double tb = 0.0;
-            if (top) {
-                tb = obar;
-            } else if (ones) {
-                const int h = __builtin_ctz(ones);
-                const int sh = (M.subb >> h) & 1u;
-                const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, twos | (1u << h));
-                // mask-only: the first cycle's successor lives on plane 1 only
-                for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
-                    tb += lane_ld(Bn + k * cpl + (int64_t)crow * D * 64 + (2 * h + sh) * 64, lane8);
-            }
-            tb *= A.W;
             const bool full0 = twos & 1u;
             uint32_t hs = full0 ? (twos & ~1u) : 0u;   // heads >= 1, ascending
             int u = 0, su = full0 ? 0 : (int)(M.subb & 1u), slot = 0;
-            while (true) {
-                if (!(MASK && u == 0 && ((lam == 0) == full0)))
-                    sub_adj_row<N, MASK>(M, gaddr, gbaddr, FL, BnL, BcL, lane8, u, su, M.rb + slot, start, tb, i0);
-                ++slot;
-                if (full0 && su == 0) {
-                    su = 1;
-                    continue;
+            bool go = true, one = false;
+            if (A.row_items) {
+                // this item's row alone.  The rows of a mask: (0, s_0) alone
+                // while vertex 0 is once visited; once it is full, (0, 0),
+                // (0, 1), then (h, 0), (h, 1) for the heads h >= 1 in order
+                const int k = it - mi * RPM;
+                one = true;
+                if (k > 0) {
+                    go = full0;
+                    if (full0) {
+                        const int j = k >> 1;   // 0: vertex 0; j >= 1: the j-th head >= 1
+                        for (int q = 1; q < j; ++q) hs &= hs - 1u;
+                        if (j > 0) {
+                            go = hs != 0;   // the mask has fewer rows
+                            u = go ? __builtin_ctz(hs) : 0;
+                        }
+                        su = k & 1;
+                    }
+                    slot = k;
                 }
-                if (!hs) break;
-                u = __builtin_ctz(hs);
-                hs &= hs - 1u;
-                su = 0;
+            }
+            if (go) {
+                double tb = 0.0;
+                if (top) {
+                    tb = obar;
+                } else if (ones) {
+                    const int h = __builtin_ctz(ones);
+                    const int sh = (M.subb >> h) & 1u;
+                    const int crow = sub_child_base<N>(M, 2 * h + sh) + sub_head_slot(h, sh, twos | (1u << h));
+                    // mask-only: the first cycle's successor lives on plane 1 only
+                    for (int k = (MASK && h == 0 ? 1 : 0); k < nfs; ++k)
+                        tb += lane_ld(Bn + k * cpl + (int64_t)crow * D * 64 + (2 * h + sh) * 64, lane8);
+                }
+                tb *= A.W;
+                while (true) {
+                    if (!(MASK && u == 0 && ((lam == 0) == full0)))
+                        sub_adj_row<N, MASK>(M, gaddr, gbaddr, FL, BnL, BcL, lane8, u, su, M.rb + slot, start, tb, i0);
+                    if (one) break;
+                    ++slot;
+                    if (full0 && su == 0) {
+                        su = 1;
+                        continue;
+                    }
+                    if (!hs) break;
+                    u = __builtin_ctz(hs);
+                    hs &= hs - 1u;
+                    su = 0;
+                }
             }
             int nx = 0;
             if (lane == 0) nx = atomicAdd(&next_mask, 1);
-            mi = COS_RF(nx);   // lane 0's claim (every lane is active here)
+            it = COS_RF(nx);   // lane 0's claim (every lane is active here)
         }
         __syncthreads();
         double *__restrict__ gb = A.Gbar_T + (int64_t)(g * nfs + lam) * D * D * 64 + (int64_t)i0 * D * 64;

@@ -1027,11 +1027,12 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                 a.F_row0 = (int32_t)srow(l, upper);
                 const int nm = o.hp->levels[l].w;
                 // a level whose masks fill at most half the wavefronts of one
-                // round, and whose masks hold at least n / 2 rows on average
-                // (the upper levels), gives every row a wavefront of its own
-                a.row_items = (!o.sub && (int64_t)nm * cg * 2 <= (int64_t)b->ncu * 16 &&
-                               2 * level_rows(*o.hp, l, l) >= (int64_t)nm * o.n) ? 1 : 0;
-                const int items = a.row_items ? nm * o.n : nm;
+                // round, and whose masks hold at least half the most rows a
+                // mask can have (n, labelled 2n) on average (the upper
+                // levels), gives every row a wavefront of its own
+                a.row_items = ((int64_t)nm * cg * 2 <= (int64_t)b->ncu * 16 &&
+                               2 * level_rows(*o.hp, l, l) >= (int64_t)nm * o.slots()) ? 1 : 0;
+                const int items = a.row_items ? nm * o.slots() : nm;
                 a.mpb = adj_masks(o.shape, items, cg, b->ncu);
                 a.out_bar = d_out_bar;
                 a.Gbar_T = GbT;
@@ -1043,7 +1044,7 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                     LAUNCH_TRY(launch_level_det(a, cg, s));
                     continue;
                 }
-                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (nm + a.mpb - 1) / a.mpb, cg, s));
+                if (o.sub) LAUNCH_TRY(launch_sub_adj_level(a, (items + a.mpb - 1) / a.mpb, cg, s));
                 else LAUNCH_TRY(launch_level(a, true, (items + a.mpb - 1) / a.mpb, cg, adj_waves_per_block(), s));
             }
             return COS_OK;
