@@ -1027,10 +1027,13 @@ static cos_status adjoint_order(cos_batch_t b, const OrderGroup &o, const double
                 a.F_row0 = (int32_t)srow(l, upper);
                 const int nm = o.hp->levels[l].w;
                 // a level whose masks fill at most half the wavefronts of one
-                // round, and whose masks hold at least half the most rows a
-                // mask can have (n, labelled 2n) on average (the upper
-                // levels), gives every row a wavefront of its own
-                a.row_items = ((int64_t)nm * cg * 2 <= (int64_t)b->ncu * 16 &&
+                // round (labelled: an eighth; its rows are split over two
+                // workgroups at n = 7, 8 and each row reloads its mask's close
+                // adjoints in every flavour), and whose masks hold at least
+                // half the most rows a mask can have (n, labelled 2n) on
+                // average (the upper levels), gives every row a wavefront of its own
+                const int64_t fill = o.sub ? 8 : 2;
+                a.row_items = ((int64_t)nm * cg * fill <= (int64_t)b->ncu * 16 &&
                                2 * level_rows(*o.hp, l, l) >= (int64_t)nm * o.slots()) ? 1 : 0;
                 const int items = a.row_items ? nm * o.slots() : nm;
                 a.mpb = adj_masks(o.shape, items, cg, b->ncu);
